@@ -1,0 +1,193 @@
+/*
+ * wt.h -- C ABI of the MI355X (gfx950) wavelet tree / wavelet matrix library.
+ *
+ * Builds, on the GPU, the level-wise wavelet tree (WT) and the wavelet matrix
+ * (WM) of an integer text T[0,n) over [0, 2^lg_sigma), bottom-up as in
+ * Fischer, Kurpicz, Loebel, "Simple, Fast and Lightweight Parallel Wavelet Tree
+ * Construction" (arXiv 1702.07578): prefix histograms per tile of the text
+ * (Section 3.2, per-core histograms of Algorithm 2), merged upward level by
+ * level (Algorithm 1, histogram update), interval starts by a zero-based prefix
+ * sum over (key, tile) in prefix order for the WT and bit-reversed order for
+ * the WM (Section 3.2 and Section 5.1), and a stable scatter of every level's
+ * bits into place (Algorithm 1, bit placement).  It also builds binary
+ * rank/select directories over every level and answers batched access, rank
+ * and select queries (Section 2 and Section 5: O(lg sigma) walks).
+ *
+ * Conventions (every call):
+ *   - Pointers named d_* and all pointers inside wt_levels are DEVICE pointers;
+ *     everything else is host memory.
+ *   - The caller owns all memory.  The library never allocates or frees device
+ *     memory: outputs live in one caller buffer carved by wt_levels_bind, and
+ *     temporaries in a caller workspace sized by wt_workspace_bytes.
+ *   - Every device call is asynchronous on the given stream; buffers must stay
+ *     alive until the stream has passed the call.  Calls on different streams
+ *     must use different workspaces.
+ *   - Host-detected errors return immediately with a negative code and enqueue
+ *     nothing.  A symbol >= 2^lg_sigma is detected on the device: the build
+ *     completes (with unspecified level contents) and sets the status word,
+ *     read by wt_get_status.
+ *   - Limits: n < 2^32 (positions fit 32 bits), lg_sigma <= 32, sym_bytes in
+ *     {1, 2, 4}.  The WT with lg_sigma > WT_MAX_TREE_LEVELS returns
+ *     WT_ENOTSUP (its deep levels use dense per-prefix interval tables).
+ *
+ * Bit layout of a level: position p is bit p%64 of 64-bit word p/64 (LSB
+ * first); words_per_level = ceil(n/64) rounded up to a multiple of 8; all bits
+ * at positions >= n are zero.  Level l holds bit l (MSB first) of the symbols:
+ * bit(l, a) = (a >> (lg_sigma - 1 - l)) & 1 (Section 2).
+ */
+#ifndef WT_H
+#define WT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status / error codes */
+#define WT_OK 0
+#define WT_EINVAL (-1)   /* bad argument: null pointer, sym_bytes, lg_sigma, n, kind */
+#define WT_ENOSPACE (-2) /* output or workspace buffer too small */
+#define WT_ERANGE (-3)   /* a symbol is >= 2^lg_sigma (device-detected) */
+#define WT_EHIP (-4)     /* a HIP runtime call failed */
+#define WT_ENOTSUP (-5)  /* valid but unsupported configuration */
+
+#define WT_MAX_TREE_LEVELS 26
+/* one select sample per WT_SEL_SPACING ones (zeros) of a level */
+#define WT_SEL_SPACING 4096u
+
+typedef enum { WT_TREE = 0, WT_MATRIX = 1 } wt_kind;
+
+/*
+ * Non-owning view of a built (or to-be-built) structure, filled by
+ * wt_levels_bind.  All arrays are in device memory inside the bound buffer.
+ *   bits      [lg_sigma][words_per_level] level bit vectors (layout above).
+ *   zeros     [lg_sigma] number of zeros of each level (Z of Section 5; also
+ *             filled for the WT, where it is the same count).
+ *   rank_dir  [lg_sigma][rank_stride]: entry j (0 <= j <= words_per_level/8)
+ *             is the number of ones in bits [0, 512 j) of the level.
+ *   sel0/sel1 [lg_sigma][sel_stride]: entry q is the index of the 512-bit
+ *             block holding the (q*WT_SEL_SPACING + 1)-th zero / one of the
+ *             level (positions < n only); 0xFFFFFFFF past the last sample.
+ *   status    one int32: WT_OK or WT_ERANGE after a build.
+ */
+typedef struct wt_levels {
+    uint64_t n;
+    uint32_t lg_sigma;
+    uint32_t kind; /* wt_kind */
+    uint64_t words_per_level;
+    uint64_t rank_stride; /* uint32 entries per level in rank_dir */
+    uint64_t sel_stride;  /* uint32 entries per level in sel0 / sel1 */
+    uint64_t *bits;
+    uint64_t *zeros;
+    uint32_t *rank_dir;
+    uint32_t *sel0;
+    uint32_t *sel1;
+    int32_t *status;
+} wt_levels;
+
+/* Optional tuning knobs; zero fields mean "choose automatically". */
+typedef struct wt_tune {
+    uint32_t tile_log2;  /* log2 of symbols per tile, 10..16 */
+    uint32_t group_bits; /* levels handled per pass over the text, 1..8 */
+    uint32_t grid;       /* workgroups of the tile kernels (0: one per tile) */
+    uint32_t reserved;
+} wt_tune;
+
+/* Bytes of the output buffer for a text of length n over lg_sigma levels
+ * (same for the WT and the WM).  Host only. */
+size_t wt_output_bytes(uint64_t n, uint32_t lg_sigma);
+
+/* Bytes of device workspace a build needs.  Host only.  0 with tune NULL is
+ * never returned for a valid configuration; returns 0 for an invalid one. */
+size_t wt_workspace_bytes(uint64_t n, uint32_t sym_bytes, uint32_t lg_sigma, wt_kind kind);
+size_t wt_workspace_bytes_tuned(uint64_t n, uint32_t sym_bytes, uint32_t lg_sigma, wt_kind kind,
+                                const wt_tune *tune);
+
+/* Carve a caller device buffer of `bytes` bytes at d_mem (256-byte aligned)
+ * into a wt_levels view.  Host only; touches no device memory.
+ * WT_EINVAL / WT_ENOSPACE on bad arguments. */
+int wt_levels_bind(wt_levels *out, void *d_mem, size_t bytes, uint64_t n, uint32_t lg_sigma,
+                   wt_kind kind);
+
+/*
+ * Build the wavelet tree (wt_build) or the wavelet matrix (wm_build) of the
+ * device text d_text[0,n) of sym_bytes-byte unsigned symbols, plus Z and the
+ * rank/select directories, into *out (bound with the same n, lg_sigma and the
+ * matching kind).  d_ws/ws_bytes: device workspace of at least
+ * wt_workspace_bytes(...).  Asynchronous on `stream`.
+ */
+int wt_build(const void *d_text, uint64_t n, uint32_t sym_bytes, uint32_t lg_sigma,
+             wt_levels *out, void *d_ws, size_t ws_bytes, hipStream_t stream);
+int wm_build(const void *d_text, uint64_t n, uint32_t sym_bytes, uint32_t lg_sigma,
+             wt_levels *out, void *d_ws, size_t ws_bytes, hipStream_t stream);
+/* Same, with tuning knobs (tune may be NULL). */
+int wt_build_tuned(wt_kind kind, const void *d_text, uint64_t n, uint32_t sym_bytes,
+                   uint32_t lg_sigma, wt_levels *out, void *d_ws, size_t ws_bytes,
+                   const wt_tune *tune, hipStream_t stream);
+
+/*
+ * Batched queries over a built structure s (WT or WM, by s->kind), m queries,
+ * one result each, asynchronous on `stream`.
+ *   access(i) = T[i]; 0xFFFFFFFF if i >= n.
+ *   rank(c, i) = number of c in T[0,i) (Section 2); UINT64_MAX if i > n;
+ *                0 if c >= 2^lg_sigma.
+ *   select(c, k) = position of the k-th c (k >= 1, 0-based result);
+ *                UINT64_MAX if k = 0, c >= 2^lg_sigma or k > rank(c, n).
+ */
+int wt_access(const wt_levels *s, const uint64_t *d_pos, uint64_t m, uint32_t *d_out,
+              hipStream_t stream);
+int wt_rank(const wt_levels *s, const uint32_t *d_sym, const uint64_t *d_pos, uint64_t m,
+            uint64_t *d_out, hipStream_t stream);
+int wt_select(const wt_levels *s, const uint32_t *d_sym, const uint64_t *d_k, uint64_t m,
+              uint64_t *d_out, hipStream_t stream);
+
+/* Synchronise `stream` and return the status word of s: WT_OK or WT_ERANGE
+ * (or WT_EHIP if the synchronisation failed). */
+int wt_get_status(const wt_levels *s, hipStream_t stream);
+
+/* Static message for a code. */
+const char *wt_strerror(int code);
+
+/*
+ * Batched build: `count` independent texts, each with its own length, symbol
+ * width, lg_sigma, kind and output view, built by one sequence of launches
+ * whose tile kernels loop over the (text, tile) work items of every text.
+ * d_ws: workspace of wt_batch_workspace_bytes(items, count, tune) bytes.
+ * Per-text descriptors are copied into the workspace from host memory with a
+ * synchronous copy before any kernel is enqueued.
+ */
+typedef struct wt_batch_item {
+    const void *d_text;
+    uint64_t n;
+    uint32_t sym_bytes;
+    uint32_t lg_sigma;
+    uint32_t kind;  /* wt_kind */
+    uint32_t reserved;
+    wt_levels *out; /* host pointer to a bound view */
+} wt_batch_item;
+
+size_t wt_batch_workspace_bytes(const wt_batch_item *items, uint32_t count, const wt_tune *tune);
+int wt_batch_build(const wt_batch_item *items, uint32_t count, void *d_ws, size_t ws_bytes,
+                   const wt_tune *tune, hipStream_t stream);
+
+/*
+ * Profiling aid: run one build like wt_build_tuned, recording a HIP event
+ * after every kernel, wait for it, and add each kernel's duration to
+ * ms_by_kernel[id] (ids: see wt_kernel_name; n_ids entries, >= WT_NUM_KERNEL_IDS)
+ * and its launch count to launches_by_kernel[id].  Synchronous.
+ */
+#define WT_NUM_KERNEL_IDS 16
+int wt_build_profiled(wt_kind kind, const void *d_text, uint64_t n, uint32_t sym_bytes,
+                      uint32_t lg_sigma, wt_levels *out, void *d_ws, size_t ws_bytes,
+                      const wt_tune *tune, hipStream_t stream, double *ms_by_kernel,
+                      uint32_t *launches_by_kernel, uint32_t n_ids);
+const char *wt_kernel_name(uint32_t id);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WT_H */

@@ -1,0 +1,600 @@
+// C ABI (include/wt.h): argument checks, sizing, output binding, workspace
+// planning and the launch sequence of a build.  No device memory is allocated
+// here; every buffer comes from the caller.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "wt_internal.h"
+
+namespace wtg {
+
+static inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+static inline uint64_t cdiv64(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+static inline uint64_t words_per_level(uint64_t n) { return align_up(cdiv64(n, 64), 8); }
+static inline uint64_t rank_stride(uint64_t n) { return align_up(words_per_level(n) / 8 + 1, 16); }
+static inline uint64_t sel_stride(uint64_t n) { return align_up(cdiv64(n, WT_SEL_SPACING) + 1, 16); }
+
+static uint32_t log2_floor(uint64_t x)
+{
+    uint32_t r = 0;
+    while (x > 1) {
+        x >>= 1;
+        r++;
+    }
+    return r;
+}
+
+static int check_args(uint64_t n, uint32_t b, uint32_t L, uint32_t kind)
+{
+    if (b != 1 && b != 2 && b != 4) return WT_EINVAL;
+    if (L > 32) return WT_EINVAL;
+    if (n >= (1ull << 32)) return WT_EINVAL;
+    if (kind != WT_TREE && kind != WT_MATRIX) return WT_EINVAL;
+    if (kind == WT_TREE && L > WT_MAX_TREE_LEVELS) return WT_ENOTSUP;
+    return WT_OK;
+}
+
+// Output layout, offsets relative to a 256-byte aligned start.
+struct OutLayout {
+    uint64_t W, rs, ss;
+    uint64_t o_bits, o_zeros, o_rank, o_sel0, o_sel1, o_status, total;
+};
+
+static OutLayout out_layout(uint64_t n, uint32_t L)
+{
+    OutLayout o;
+    o.W = words_per_level(n);
+    o.rs = rank_stride(n);
+    o.ss = sel_stride(n);
+    uint64_t off = 0;
+    o.o_bits = off;
+    off = align_up(off + (uint64_t)L * o.W * 8, 256);
+    o.o_zeros = off;
+    off = align_up(off + (uint64_t)L * 8, 256);
+    o.o_rank = off;
+    off = align_up(off + (uint64_t)L * o.rs * 4, 256);
+    o.o_sel0 = off;
+    off = align_up(off + (uint64_t)L * o.ss * 4, 256);
+    o.o_sel1 = off;
+    off = align_up(off + (uint64_t)L * o.ss * 4, 256);
+    o.o_status = off;
+    off = align_up(off + 4, 256);
+    o.total = off;
+    return o;
+}
+
+// Workspace plan of one text: descriptor fields and region offsets relative
+// to the text's region start.
+struct WsPlan {
+    TextDesc d;  // pointer fields hold offsets until bound
+    uint64_t o_H, o_TP, o_CS, o_KBid, o_KBpi, o_HT, o_seqA, o_seqB, o_tmpb, o_tmpr, o_walk,
+        o_bc, o_cs;
+    uint64_t bytes;
+};
+
+static int plan_text(uint64_t n, uint32_t b, uint32_t L, uint32_t kind, const wt_tune *tune,
+                     WsPlan &p)
+{
+    int rc = check_args(n, b, L, kind);
+    if (rc != WT_OK) return rc;
+    std::memset(&p, 0, sizeof(p));
+    TextDesc &d = p.d;
+    d.n = n;
+    d.b = b;
+    d.L = L;
+    d.kind = kind;
+    uint32_t K = (tune && tune->group_bits) ? std::min<uint32_t>(tune->group_bits, kMaxGroupBits)
+                                            : kMaxGroupBits;
+    if (K == 0) K = 1;
+    if (L > 0 && K > L) K = L;
+    d.K = K;
+    d.G = (L == 0) ? 1 : (uint32_t)cdiv64(L, K);
+    const uint32_t smax = log2_floor(kTileBufBytes / b);
+    uint32_t ls;
+    if (tune && tune->tile_log2) ls = tune->tile_log2;
+    else ls = (uint32_t)std::max<int64_t>(10, (int64_t)log2_floor(n ? n : 1) - 8);
+    ls = std::min(std::max(ls, 10u), smax);
+    d.log2S = ls;
+    d.ntiles = (uint32_t)cdiv64(n, 1ull << ls);
+    uint32_t ch = 1;
+    while ((uint64_t)ch * ch < d.ntiles) ch <<= 1;
+    d.CH = ch;
+    d.nchunks = (uint32_t)cdiv64(d.ntiles, ch);
+    d.W = words_per_level(n);
+    d.nb = d.W / 8;
+    d.rank_stride = rank_stride(n);
+    d.sel_stride = sel_stride(n);
+    d.dir_chunks = (uint32_t)cdiv64(d.nb, kDirChunk);
+
+    const uint64_t nk = 1ull << K;
+    const bool deep_wt = (kind == WT_TREE && d.G > 1);
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) {
+        uint64_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    };
+    p.o_H = take((uint64_t)d.ntiles * nk * 4);
+    p.o_TP = take((uint64_t)d.ntiles * nk * 4);
+    p.o_CS = take((uint64_t)d.nchunks * nk * 4);
+    p.o_KBid = take((2 * nk) * 4);
+    p.o_KBpi = take((2 * nk) * 4);
+    p.o_HT = take((2 * nk) * 4);
+    p.o_seqA = take(d.G > 1 ? n * b : 0);
+    p.o_seqB = take(d.G > 2 ? n * b : 0);
+    p.o_tmpb = take(deep_wt ? (uint64_t)(L - K) * d.W * 8 : 0);
+    p.o_tmpr = take(deep_wt ? (uint64_t)(L - K) * d.rank_stride * 4 : 0);
+    p.o_walk = take(deep_wt ? walk_off(K, L) * 4 : 0);
+    p.o_bc = take((uint64_t)L * d.nb * 2);
+    p.o_cs = take((uint64_t)L * d.dir_chunks * 4);
+    p.bytes = off;
+    return WT_OK;
+}
+
+static void bind_ws(WsPlan &p, uint8_t *base)
+{
+    TextDesc &d = p.d;
+    d.H = (uint32_t *)(base + p.o_H);
+    d.TP = (uint32_t *)(base + p.o_TP);
+    d.CS = (uint32_t *)(base + p.o_CS);
+    d.KBid = (uint32_t *)(base + p.o_KBid);
+    d.KBpi = (uint32_t *)(base + p.o_KBpi);
+    d.HT = (uint32_t *)(base + p.o_HT);
+    d.seqA = base + p.o_seqA;
+    d.seqB = base + p.o_seqB;
+    d.tmp_bits = (uint64_t *)(base + p.o_tmpb);
+    d.tmp_rank = (uint32_t *)(base + p.o_tmpr);
+    d.walk = (uint32_t *)(base + p.o_walk);
+    d.dir_bc = (uint16_t *)(base + p.o_bc);
+    d.dir_cs = (uint32_t *)(base + p.o_cs);
+}
+
+static void bind_out(TextDesc &d, const wt_levels &o)
+{
+    d.bits = o.bits;
+    d.zeros = o.zeros;
+    d.rank_dir = o.rank_dir;
+    d.sel0 = o.sel0;
+    d.sel1 = o.sel1;
+    d.status = o.status;
+}
+
+static int check_out(const wt_levels *out, uint64_t n, uint32_t L, uint32_t kind)
+{
+    if (!out) return WT_EINVAL;
+    if (out->n != n || out->lg_sigma != L || out->kind != kind) return WT_EINVAL;
+    if (!out->status) return WT_EINVAL;
+    if (L > 0 && (!out->bits || !out->zeros || !out->rank_dir || !out->sel0 || !out->sel1))
+        return WT_EINVAL;
+    if (out->words_per_level != words_per_level(n) || out->rank_stride != rank_stride(n) ||
+        out->sel_stride != sel_stride(n))
+        return WT_EINVAL;
+    return WT_OK;
+}
+
+// Launch counts of a set of texts (one build or a batch).
+struct Sched {
+    uint32_t nd = 0;
+    uint32_t gmax = 0;
+    uint32_t ntiles = 0, nchunks = 0;
+    std::vector<bool> any_levels;  // per group
+    uint32_t dir_items = 0, tmpdir_items = 0, max_levels = 0, max_tmp_levels = 0;
+    std::vector<uint32_t> walk_items;  // per step
+    uint32_t gather_items = 0;
+    // host prefix arrays (nd + 1 each), only needed for nd > 1
+    std::vector<uint32_t> b_tiles, b_chunks, b_dir, b_tmpdir, b_gather;
+    std::vector<std::vector<uint32_t>> b_walk;
+};
+
+static int schedule(const std::vector<TextDesc> &ds, Sched &s)
+{
+    s.nd = (uint32_t)ds.size();
+    uint32_t max_steps = 0;
+    for (const TextDesc &d : ds) {
+        s.gmax = std::max(s.gmax, d.G);
+        if (d.kind == WT_TREE && d.G > 1) max_steps = std::max(max_steps, d.L - d.K - 1);
+    }
+    s.any_levels.assign(s.gmax, false);
+    s.walk_items.assign(max_steps, 0);
+    s.b_walk.assign(max_steps, {});
+    auto push = [](std::vector<uint32_t> &v, uint64_t &acc, uint64_t add) {
+        v.push_back((uint32_t)acc);
+        acc += add;
+    };
+    uint64_t at = 0, ac = 0, adir = 0, atmp = 0, aga = 0;
+    std::vector<uint64_t> aw(max_steps, 0);
+    for (const TextDesc &d : ds) {
+        const bool deep = (d.kind == WT_TREE && d.G > 1);
+        push(s.b_tiles, at, d.ntiles);
+        push(s.b_chunks, ac, d.nchunks);
+        push(s.b_dir, adir, (uint64_t)d.L * d.dir_chunks);
+        push(s.b_tmpdir, atmp, deep ? (uint64_t)(d.L - d.K) * d.dir_chunks : 0);
+        push(s.b_gather, aga, deep ? (uint64_t)(d.L - d.K) * d.W : 0);
+        for (uint32_t st = 0; st < max_steps; st++) {
+            const bool has = deep && (d.K + st + 1 < d.L);
+            push(s.b_walk[st], aw[st], has ? (1ull << (d.K + st)) : 0);
+        }
+        for (uint32_t g = 0; g < d.G; g++)
+            if (group_bits(d, g) > 0) s.any_levels[g] = true;
+        s.max_levels = std::max(s.max_levels, d.L);
+        if (deep) s.max_tmp_levels = std::max(s.max_tmp_levels, d.L - d.K);
+    }
+    s.b_tiles.push_back((uint32_t)at);
+    s.b_chunks.push_back((uint32_t)ac);
+    s.b_dir.push_back((uint32_t)adir);
+    s.b_tmpdir.push_back((uint32_t)atmp);
+    s.b_gather.push_back((uint32_t)aga);
+    for (uint32_t st = 0; st < max_steps; st++) s.b_walk[st].push_back((uint32_t)aw[st]);
+    const uint64_t lim = 0xFFFFFFFFull;
+    if (at > lim || ac > lim || adir > lim || atmp > lim || aga > lim) return WT_ENOTSUP;
+    for (uint64_t x : aw)
+        if (x > lim) return WT_ENOTSUP;
+    s.ntiles = (uint32_t)at;
+    s.nchunks = (uint32_t)ac;
+    s.dir_items = (uint32_t)adir;
+    s.tmpdir_items = (uint32_t)atmp;
+    s.gather_items = (uint32_t)aga;
+    for (uint32_t st = 0; st < max_steps; st++) s.walk_items[st] = (uint32_t)aw[st];
+    return WT_OK;
+}
+
+// Device copies of the prefix arrays (batch only); all null for one text.
+struct DevBases {
+    const uint32_t *tiles = nullptr, *chunks = nullptr, *dir = nullptr, *tmpdir = nullptr,
+                   *gather = nullptr;
+    std::vector<const uint32_t *> walk;
+};
+
+static hipError_t run_build(const TextDesc *d_descs, const Sched &s, const DevBases &b,
+                            uint32_t grid_cap, const LaunchCtx &ctx)
+{
+    hipError_t e;
+    for (uint32_t g = 0; g < s.gmax; g++) {
+        GroupLaunch gl;
+        gl.g = g;
+        gl.nd = s.nd;
+        gl.tile_bases = b.tiles;
+        gl.chunk_bases = b.chunks;
+        gl.ntiles = s.ntiles;
+        gl.nchunks = s.nchunks;
+        gl.any_levels = s.any_levels[g];
+        gl.grid_cap = grid_cap;
+        if ((e = launch_group(d_descs, gl, ctx)) != hipSuccess) return e;
+    }
+    if (s.max_tmp_levels) {
+        if ((e = launch_dirs(d_descs, b.tmpdir, s.nd, s.tmpdir_items, s.max_tmp_levels, true,
+                             grid_cap, ctx)) != hipSuccess)
+            return e;
+        for (uint32_t st = 0; st < s.walk_items.size(); st++)
+            if ((e = launch_walk(d_descs, b.walk.empty() ? nullptr : b.walk[st], s.nd,
+                                 s.walk_items[st], st, ctx)) != hipSuccess)
+                return e;
+        if ((e = launch_gather(d_descs, b.gather, s.nd, s.gather_items, ctx)) != hipSuccess)
+            return e;
+    }
+    return launch_dirs(d_descs, b.dir, s.nd, s.dir_items, s.max_levels, false, grid_cap, ctx);
+}
+
+static int build_one(wt_kind kind, const void *d_text, uint64_t n, uint32_t sym_bytes,
+                     uint32_t lg_sigma, wt_levels *out, void *d_ws, size_t ws_bytes,
+                     const wt_tune *tune, const LaunchCtx &ctx)
+{
+    WsPlan p;
+    int rc = plan_text(n, sym_bytes, lg_sigma, kind, tune, p);
+    if (rc != WT_OK) return rc;
+    if ((rc = check_out(out, n, lg_sigma, kind)) != WT_OK) return rc;
+    if (n > 0 && !d_text) return WT_EINVAL;
+    if ((uintptr_t)d_text % sym_bytes) return WT_EINVAL;
+    if (!d_ws) return WT_EINVAL;
+    const uint64_t need = p.bytes + align_up(sizeof(TextDesc), 256) + 256;
+    if (ws_bytes < need) return WT_ENOSPACE;
+    uint8_t *base = (uint8_t *)align_up((uintptr_t)d_ws, 256);
+    TextDesc *d_desc = (TextDesc *)base;
+    bind_ws(p, base + align_up(sizeof(TextDesc), 256));
+    p.d.text = d_text;
+    bind_out(p.d, *out);
+    p.d.tile_base = 0;
+    std::vector<TextDesc> ds{p.d};
+    Sched s;
+    if ((rc = schedule(ds, s)) != WT_OK) return rc;
+    if (launch_init(p.d, d_desc, ctx) != hipSuccess) return WT_EHIP;
+    DevBases b;
+    b.walk.assign(s.walk_items.size(), nullptr);
+    const uint32_t cap = tune ? tune->grid : 0;
+    if (run_build(d_desc, s, b, cap, ctx) != hipSuccess) return WT_EHIP;
+    return WT_OK;
+}
+
+}  // namespace wtg
+
+using namespace wtg;
+
+extern "C" {
+
+size_t wt_output_bytes(uint64_t n, uint32_t lg_sigma)
+{
+    if (lg_sigma > 32 || n >= (1ull << 32)) return 0;
+    return out_layout(n, lg_sigma).total + 256;
+}
+
+size_t wt_workspace_bytes_tuned(uint64_t n, uint32_t sym_bytes, uint32_t lg_sigma, wt_kind kind,
+                                const wt_tune *tune)
+{
+    WsPlan p;
+    if (plan_text(n, sym_bytes, lg_sigma, (uint32_t)kind, tune, p) != WT_OK) return 0;
+    return p.bytes + align_up(sizeof(TextDesc), 256) + 256;
+}
+
+size_t wt_workspace_bytes(uint64_t n, uint32_t sym_bytes, uint32_t lg_sigma, wt_kind kind)
+{
+    return wt_workspace_bytes_tuned(n, sym_bytes, lg_sigma, kind, nullptr);
+}
+
+int wt_levels_bind(wt_levels *out, void *d_mem, size_t bytes, uint64_t n, uint32_t lg_sigma,
+                   wt_kind kind)
+{
+    if (!out || !d_mem) return WT_EINVAL;
+    if (lg_sigma > 32 || n >= (1ull << 32)) return WT_EINVAL;
+    if (kind != WT_TREE && kind != WT_MATRIX) return WT_EINVAL;
+    OutLayout o = out_layout(n, lg_sigma);
+    uint8_t *base = (uint8_t *)align_up((uintptr_t)d_mem, 256);
+    if ((uint64_t)(base - (uint8_t *)d_mem) + o.total > bytes) return WT_ENOSPACE;
+    out->n = n;
+    out->lg_sigma = lg_sigma;
+    out->kind = (uint32_t)kind;
+    out->words_per_level = o.W;
+    out->rank_stride = o.rs;
+    out->sel_stride = o.ss;
+    out->bits = (uint64_t *)(base + o.o_bits);
+    out->zeros = (uint64_t *)(base + o.o_zeros);
+    out->rank_dir = (uint32_t *)(base + o.o_rank);
+    out->sel0 = (uint32_t *)(base + o.o_sel0);
+    out->sel1 = (uint32_t *)(base + o.o_sel1);
+    out->status = (int32_t *)(base + o.o_status);
+    return WT_OK;
+}
+
+int wt_build_tuned(wt_kind kind, const void *d_text, uint64_t n, uint32_t sym_bytes,
+                   uint32_t lg_sigma, wt_levels *out, void *d_ws, size_t ws_bytes,
+                   const wt_tune *tune, hipStream_t stream)
+{
+    LaunchCtx ctx{stream, nullptr, nullptr};
+    return build_one(kind, d_text, n, sym_bytes, lg_sigma, out, d_ws, ws_bytes, tune, ctx);
+}
+
+int wt_build(const void *d_text, uint64_t n, uint32_t sym_bytes, uint32_t lg_sigma,
+             wt_levels *out, void *d_ws, size_t ws_bytes, hipStream_t stream)
+{
+    return wt_build_tuned(WT_TREE, d_text, n, sym_bytes, lg_sigma, out, d_ws, ws_bytes, nullptr,
+                          stream);
+}
+
+int wm_build(const void *d_text, uint64_t n, uint32_t sym_bytes, uint32_t lg_sigma,
+             wt_levels *out, void *d_ws, size_t ws_bytes, hipStream_t stream)
+{
+    return wt_build_tuned(WT_MATRIX, d_text, n, sym_bytes, lg_sigma, out, d_ws, ws_bytes, nullptr,
+                          stream);
+}
+
+static int query_common(const wt_levels *s, int op, const uint32_t *d_sym, const uint64_t *d_arg,
+                        uint64_t m, void *d_out, hipStream_t stream)
+{
+    if (!s || (m > 0 && (!d_arg || !d_out || (op != 0 && !d_sym)))) return WT_EINVAL;
+    if (s->kind != WT_TREE && s->kind != WT_MATRIX) return WT_EINVAL;
+    if (s->lg_sigma > 32 || s->n >= (1ull << 32)) return WT_EINVAL;
+    if (m >= (1ull << 38)) return WT_EINVAL;
+    LaunchCtx ctx{stream, nullptr, nullptr};
+    return launch_queries(*s, op, d_sym, d_arg, m, d_out, ctx) == hipSuccess ? WT_OK : WT_EHIP;
+}
+
+int wt_access(const wt_levels *s, const uint64_t *d_pos, uint64_t m, uint32_t *d_out,
+              hipStream_t stream)
+{
+    return query_common(s, 0, nullptr, d_pos, m, d_out, stream);
+}
+
+int wt_rank(const wt_levels *s, const uint32_t *d_sym, const uint64_t *d_pos, uint64_t m,
+            uint64_t *d_out, hipStream_t stream)
+{
+    return query_common(s, 1, d_sym, d_pos, m, d_out, stream);
+}
+
+int wt_select(const wt_levels *s, const uint32_t *d_sym, const uint64_t *d_k, uint64_t m,
+              uint64_t *d_out, hipStream_t stream)
+{
+    return query_common(s, 2, d_sym, d_k, m, d_out, stream);
+}
+
+int wt_get_status(const wt_levels *s, hipStream_t stream)
+{
+    if (!s || !s->status) return WT_EINVAL;
+    int32_t st = 0;
+    if (hipMemcpyAsync(&st, s->status, sizeof(st), hipMemcpyDeviceToHost, stream) != hipSuccess)
+        return WT_EHIP;
+    if (hipStreamSynchronize(stream) != hipSuccess) return WT_EHIP;
+    return st;
+}
+
+const char *wt_strerror(int code)
+{
+    switch (code) {
+    case WT_OK: return "ok";
+    case WT_EINVAL: return "invalid argument";
+    case WT_ENOSPACE: return "buffer too small";
+    case WT_ERANGE: return "symbol out of range for lg_sigma";
+    case WT_EHIP: return "HIP runtime error";
+    case WT_ENOTSUP: return "unsupported configuration";
+    default: return "unknown error";
+    }
+}
+
+// ---- batch -----------------------------------------------------------------
+
+struct BatchPlan {
+    std::vector<WsPlan> plans;
+    uint64_t o_desc, o_bases, n_bases, o_texts, total;
+};
+
+static int plan_batch(const wt_batch_item *items, uint32_t count, const wt_tune *tune,
+                      BatchPlan &bp, Sched *sched)
+{
+    if (!items || count == 0) return WT_EINVAL;
+    bp.plans.resize(count);
+    std::vector<TextDesc> ds(count);
+    uint64_t off_texts = 0;
+    std::vector<uint64_t> text_off(count);
+    for (uint32_t i = 0; i < count; i++) {
+        int rc = plan_text(items[i].n, items[i].sym_bytes, items[i].lg_sigma, items[i].kind, tune,
+                           bp.plans[i]);
+        if (rc != WT_OK) return rc;
+        text_off[i] = off_texts;
+        off_texts = align_up(off_texts + bp.plans[i].bytes, 256);
+        ds[i] = bp.plans[i].d;
+    }
+    Sched s;
+    int rc = schedule(ds, s);
+    if (rc != WT_OK) return rc;
+    uint64_t nb = 5ull * (count + 1) + (uint64_t)s.walk_items.size() * (count + 1);
+    bp.o_desc = 0;
+    bp.o_bases = align_up((uint64_t)count * sizeof(TextDesc), 256);
+    bp.n_bases = nb;
+    bp.o_texts = align_up(bp.o_bases + nb * 4, 256);
+    bp.total = bp.o_texts + off_texts + 256;
+    for (uint32_t i = 0; i < count; i++) bp.plans[i].d.tile_base = s.b_tiles[i];
+    // stash text offsets in the plan (reuse the bytes field as offset)
+    for (uint32_t i = 0; i < count; i++) bp.plans[i].bytes = text_off[i];
+    if (sched) *sched = std::move(s);
+    return WT_OK;
+}
+
+size_t wt_batch_workspace_bytes(const wt_batch_item *items, uint32_t count, const wt_tune *tune)
+{
+    BatchPlan bp;
+    if (plan_batch(items, count, tune, bp, nullptr) != WT_OK) return 0;
+    return bp.total;
+}
+
+static int batch_build(const wt_batch_item *items, uint32_t count, void *d_ws, size_t ws_bytes,
+                       const wt_tune *tune, const LaunchCtx &ctx)
+{
+    BatchPlan bp;
+    Sched s;
+    int rc = plan_batch(items, count, tune, bp, &s);
+    if (rc != WT_OK) return rc;
+    if (!d_ws) return WT_EINVAL;
+    if (ws_bytes < bp.total) return WT_ENOSPACE;
+    uint8_t *base = (uint8_t *)align_up((uintptr_t)d_ws, 256);
+    std::vector<TextDesc> ds(count);
+    for (uint32_t i = 0; i < count; i++) {
+        const wt_batch_item &it = items[i];
+        if ((rc = check_out(it.out, it.n, it.lg_sigma, it.kind)) != WT_OK) return rc;
+        if (it.n > 0 && !it.d_text) return WT_EINVAL;
+        if ((uintptr_t)it.d_text % it.sym_bytes) return WT_EINVAL;
+        WsPlan &p = bp.plans[i];
+        bind_ws(p, base + bp.o_texts + p.bytes);
+        p.d.text = it.d_text;
+        bind_out(p.d, *it.out);
+        ds[i] = p.d;
+    }
+    // host image of descriptors + prefix arrays
+    std::vector<uint8_t> img(bp.o_texts);
+    std::memcpy(img.data() + bp.o_desc, ds.data(), count * sizeof(TextDesc));
+    uint32_t *bases = (uint32_t *)(img.data() + bp.o_bases);
+    uint32_t *dbases = (uint32_t *)(base + bp.o_bases);
+    DevBases db;
+    uint64_t k = 0;
+    auto put = [&](const std::vector<uint32_t> &v) {
+        std::memcpy(bases + k, v.data(), v.size() * 4);
+        const uint32_t *p = dbases + k;
+        k += v.size();
+        return p;
+    };
+    db.tiles = put(s.b_tiles);
+    db.chunks = put(s.b_chunks);
+    db.dir = put(s.b_dir);
+    db.tmpdir = put(s.b_tmpdir);
+    db.gather = put(s.b_gather);
+    for (auto &w : s.b_walk) db.walk.push_back(put(w));
+    if (hipMemcpyAsync(base, img.data(), img.size(), hipMemcpyHostToDevice, ctx.stream) != hipSuccess)
+        return WT_EHIP;
+    if (hipStreamSynchronize(ctx.stream) != hipSuccess) return WT_EHIP;
+    const TextDesc *d_descs = (const TextDesc *)(base + bp.o_desc);
+    if (launch_init_batch(d_descs, count, ctx) != hipSuccess) return WT_EHIP;
+    const uint32_t cap = tune ? tune->grid : 0;
+    if (run_build(d_descs, s, db, cap, ctx) != hipSuccess) return WT_EHIP;
+    return WT_OK;
+}
+
+int wt_batch_build(const wt_batch_item *items, uint32_t count, void *d_ws, size_t ws_bytes,
+                   const wt_tune *tune, hipStream_t stream)
+{
+    LaunchCtx ctx{stream, nullptr, nullptr};
+    return batch_build(items, count, d_ws, ws_bytes, tune, ctx);
+}
+
+// ---- profiling ---------------------------------------------------------------
+
+struct ProfState {
+    hipStream_t stream;
+    std::vector<hipEvent_t> ev;
+    std::vector<uint32_t> kid;
+    bool failed = false;
+};
+
+static void prof_after(void *user, uint32_t kid)
+{
+    ProfState *ps = (ProfState *)user;
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) {
+        ps->failed = true;
+        return;
+    }
+    if (hipEventRecord(e, ps->stream) != hipSuccess) ps->failed = true;
+    ps->ev.push_back(e);
+    ps->kid.push_back(kid);
+}
+
+int wt_build_profiled(wt_kind kind, const void *d_text, uint64_t n, uint32_t sym_bytes,
+                      uint32_t lg_sigma, wt_levels *out, void *d_ws, size_t ws_bytes,
+                      const wt_tune *tune, hipStream_t stream, double *ms_by_kernel,
+                      uint32_t *launches_by_kernel, uint32_t n_ids)
+{
+    if (!ms_by_kernel || !launches_by_kernel || n_ids < KID_COUNT_) return WT_EINVAL;
+    ProfState ps;
+    ps.stream = stream;
+    hipEvent_t e0;
+    if (hipEventCreate(&e0) != hipSuccess) return WT_EHIP;
+    if (hipEventRecord(e0, stream) != hipSuccess) return WT_EHIP;
+    LaunchCtx ctx{stream, prof_after, &ps};
+    int rc = build_one(kind, d_text, n, sym_bytes, lg_sigma, out, d_ws, ws_bytes, tune, ctx);
+    if (hipEventSynchronize(ps.ev.empty() ? e0 : ps.ev.back()) != hipSuccess) rc = WT_EHIP;
+    if (rc == WT_OK && !ps.failed) {
+        hipEvent_t prev = e0;
+        for (size_t i = 0; i < ps.ev.size(); i++) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, prev, ps.ev[i]) != hipSuccess) rc = WT_EHIP;
+            ms_by_kernel[ps.kid[i]] += ms;
+            launches_by_kernel[ps.kid[i]] += 1;
+            prev = ps.ev[i];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    for (hipEvent_t e : ps.ev) (void)hipEventDestroy(e);
+    if (ps.failed && rc == WT_OK) rc = WT_EHIP;
+    return rc;
+}
+
+const char *wt_kernel_name(uint32_t id)
+{
+    static const char *names[] = {"init",        "hist",         "chunk_sum", "key_scan",
+                                  "tile_prefix", "zero_borders", "scatter",   "dir_count",
+                                  "dir_scan",    "dir_write",    "walk",      "gather",
+                                  "query"};
+    return id < sizeof(names) / sizeof(names[0]) ? names[id] : "unknown";
+}
+
+}  // extern "C"

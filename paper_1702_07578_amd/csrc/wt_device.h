@@ -1,0 +1,90 @@
+// Device helpers shared by the kernels: work-item to text mapping, level
+// pointers, bit reversal, wave primitives and directory-based rank.
+#pragma once
+
+#include "wt_internal.h"
+
+namespace wtg {
+
+// Map a global work item to (text index, item inside the text).  bases holds
+// ndesc + 1 prefix sums of the per-text item counts of this launch.
+__device__ inline uint32_t find_text(const uint32_t *__restrict__ bases, uint32_t nd,
+                                     uint32_t item)
+{
+    if (nd == 1) return 0;
+    uint32_t lo = 0, hi = nd;  // largest i with bases[i] <= item
+    while (hi - lo > 1) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (bases[mid] <= item) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ inline uint32_t item_base(const uint32_t *__restrict__ bases, uint32_t nd, uint32_t text)
+{
+    return nd == 1 ? 0u : bases[text];
+}
+
+// pi_a(i): reverse the a low bits of i (bit-reversal permutation, Section 5)
+__device__ inline uint32_t rev_bits(uint32_t i, uint32_t a)
+{
+    return a == 0 ? 0u : (__brev(i) >> (32u - a));
+}
+
+// Output (or temporary) bit vector of level a of group g.
+__device__ inline uint64_t *level_ptr(const TextDesc &d, uint32_t g, uint32_t a)
+{
+    uint32_t l = g * d.K + a;
+    if (d.kind == WT_TREE && g > 0) return d.tmp_bits + (uint64_t)(l - d.K) * d.W;
+    return d.bits + (uint64_t)l * d.W;
+}
+
+// The sequence a group reads: the text for group 0, then the re-ordered
+// copies (alternating buffers).
+__device__ inline const void *seq_in(const TextDesc &d, uint32_t g)
+{
+    if (g == 0) return d.text;
+    return (g & 1u) ? d.seqA : d.seqB;
+}
+
+__device__ inline void *seq_out(const TextDesc &d, uint32_t g)
+{
+    return ((g + 1u) & 1u) ? d.seqA : d.seqB;
+}
+
+// number of set bits of mask in lanes below the calling lane
+__device__ inline uint32_t mbcnt64(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ inline uint32_t lane_id() { return mbcnt64(~0ull); }
+
+// inclusive prefix sum over the 64 lanes of a wave
+__device__ inline uint32_t wave_incl_scan(uint32_t x)
+{
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (uint32_t off = 1; off < 64; off <<= 1) {
+        uint32_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    return x;
+}
+
+// ones in bits[0, i) using the 512-bit block directory rd
+__device__ inline uint64_t rank1_dir(const uint64_t *__restrict__ bits, const uint32_t *__restrict__ rd,
+                                     uint64_t i)
+{
+    uint64_t blk = i >> 9;
+    uint64_t r = rd[blk];
+    uint64_t wi = i >> 6;
+    for (uint64_t w = blk * 8; w < wi; w++) r += __popcll(bits[w]);
+    uint32_t rem = (uint32_t)(i & 63);
+    if (rem) r += __popcll(bits[wi] & ((1ull << rem) - 1));
+    return r;
+}
+
+}  // namespace wtg

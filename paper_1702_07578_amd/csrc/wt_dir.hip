@@ -1,0 +1,195 @@
+// Rank/select directories of the level bit vectors.
+//
+// The paper augments every level with binary rank and select structures
+// (Section 2 and Section 5) without fixing a layout.  This library's layout:
+//   rank_dir[j]  ones in bits [0, 512 j) of the level, j = 0 .. W/8;
+//   sel_b[q]     index of the 512-bit block that holds the (4096 q + 1)-th b
+//                among positions < n; 0xFFFFFFFF for q past the last sample.
+// Built in three launches per set of levels: ones per block (and per chunk of
+// 1024 blocks), a scan of the chunk sums per level, and the block scan that
+// writes rank_dir and the select samples.
+#include "wt_device.h"
+
+namespace wtg {
+
+// levels of a text covered by a directory launch
+__device__ inline uint32_t dir_levels(const TextDesc &d, bool tmp)
+{
+    if (!tmp) return d.L;
+    return (d.kind == WT_TREE && d.G > 1) ? d.L - d.K : 0u;
+}
+
+__device__ inline const uint64_t *dir_bits(const TextDesc &d, bool tmp, uint32_t l)
+{
+    return tmp ? d.tmp_bits + (uint64_t)l * d.W : d.bits + (uint64_t)l * d.W;
+}
+
+__device__ inline uint32_t *dir_rank(const TextDesc &d, bool tmp, uint32_t l)
+{
+    return (tmp ? d.tmp_rank : d.rank_dir) + (uint64_t)l * d.rank_stride;
+}
+
+// ones per 512-bit block and per chunk
+__global__ __launch_bounds__(256) void k_dir_count(const TextDesc *__restrict__ descs,
+                                                   const uint32_t *__restrict__ bases, uint32_t nd,
+                                                   uint32_t nitems, uint32_t tmp)
+{
+    __shared__ uint32_t red[256 / 64];
+    for (uint32_t item = blockIdx.x; item < nitems; item += gridDim.x) {
+        const uint32_t ti = find_text(bases, nd, item);
+        const TextDesc &d = descs[ti];
+        const uint32_t idx = item - item_base(bases, nd, ti);
+        if (d.dir_chunks == 0) continue;
+        const uint32_t l = idx / d.dir_chunks, c = idx % d.dir_chunks;
+        if (l >= dir_levels(d, tmp)) continue;
+        const uint64_t *bits = dir_bits(d, tmp, l);
+        uint16_t *bc = d.dir_bc + (uint64_t)l * d.nb;
+        uint32_t sum = 0;
+        for (uint32_t r = 0; r < kDirChunk / 256; r++) {
+            const uint64_t j = (uint64_t)c * kDirChunk + r * 256 + threadIdx.x;
+            if (j < d.nb) {
+                const ulonglong2 *p = (const ulonglong2 *)(bits + j * 8);
+                uint32_t x = 0;
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    ulonglong2 v = p[q];
+                    x += __popcll(v.x) + __popcll(v.y);
+                }
+                bc[j] = (uint16_t)x;
+                sum += x;
+            }
+        }
+        // block sum
+        for (uint32_t off = 32; off > 0; off >>= 1) sum += __shfl_down(sum, off, 64);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sum;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t s = 0;
+            for (uint32_t i = 0; i < 256 / 64; i++) s += red[i];
+            d.dir_cs[(uint64_t)l * d.dir_chunks + c] = s;
+        }
+        __syncthreads();
+    }
+}
+
+// per (text, level): exclusive scan of the chunk sums, final rank entry, and
+// select sample arrays reset to "absent"
+__global__ __launch_bounds__(1024) void k_dir_scan(const TextDesc *__restrict__ descs, uint32_t nd,
+                                                   uint32_t tmp)
+{
+    __shared__ uint32_t wsum[1024 / 64];
+    const TextDesc &d = descs[blockIdx.x];
+    const uint32_t l = blockIdx.y;
+    if (l >= dir_levels(d, tmp)) return;
+    uint32_t *cs = d.dir_cs + (uint64_t)l * d.dir_chunks;
+    const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    uint32_t carry = 0;
+    for (uint32_t base = 0; base < d.dir_chunks; base += 1024) {
+        const uint32_t i = base + tid;
+        const uint32_t x = i < d.dir_chunks ? cs[i] : 0u;
+        const uint32_t incl = wave_incl_scan(x);
+        if (lane == 63) wsum[w] = incl;
+        __syncthreads();
+        uint32_t pre = carry;
+        uint32_t tot = 0;
+        for (uint32_t ww = 0; ww < 1024 / 64; ww++) {
+            if (ww < w) pre += wsum[ww];
+            tot += wsum[ww];
+        }
+        if (i < d.dir_chunks) cs[i] = pre + incl - x;
+        carry += tot;
+        __syncthreads();
+    }
+    if (tid == 0) dir_rank(d, tmp, l)[d.nb] = carry;
+    if (!tmp) {
+        uint32_t *s0 = d.sel0 + (uint64_t)l * d.sel_stride;
+        uint32_t *s1 = d.sel1 + (uint64_t)l * d.sel_stride;
+        for (uint64_t q = tid; q < d.sel_stride; q += 1024) {
+            s0[q] = 0xFFFFFFFFu;
+            s1[q] = 0xFFFFFFFFu;
+        }
+    }
+}
+
+// block scan of one chunk: rank_dir entries and select samples
+__global__ __launch_bounds__(256) void k_dir_write(const TextDesc *__restrict__ descs,
+                                                   const uint32_t *__restrict__ bases, uint32_t nd,
+                                                   uint32_t nitems, uint32_t tmp)
+{
+    __shared__ uint32_t wsum[256 / 64];
+    for (uint32_t item = blockIdx.x; item < nitems; item += gridDim.x) {
+        const uint32_t ti = find_text(bases, nd, item);
+        const TextDesc &d = descs[ti];
+        const uint32_t idx = item - item_base(bases, nd, ti);
+        if (d.dir_chunks == 0) continue;
+        const uint32_t l = idx / d.dir_chunks, c = idx % d.dir_chunks;
+        if (l >= dir_levels(d, tmp)) continue;
+        const uint16_t *bc = d.dir_bc + (uint64_t)l * d.nb;
+        uint32_t *rd = dir_rank(d, tmp, l);
+        const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+        // each thread: 4 consecutive blocks
+        const uint64_t j0 = (uint64_t)c * kDirChunk + tid * 4;
+        uint32_t v[4], s = 0;
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            v[r] = (j0 + r < d.nb) ? bc[j0 + r] : 0u;
+            s += v[r];
+        }
+        const uint32_t incl = wave_incl_scan(s);
+        if (lane == 63) wsum[w] = incl;
+        __syncthreads();
+        uint32_t pre = d.dir_cs[(uint64_t)l * d.dir_chunks + c];
+        for (uint32_t ww = 0; ww < w; ww++) pre += wsum[ww];
+        pre += incl - s;
+        uint32_t *s0 = d.sel0 + (uint64_t)l * d.sel_stride;
+        uint32_t *s1 = d.sel1 + (uint64_t)l * d.sel_stride;
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const uint64_t j = j0 + r;
+            if (j < d.nb) {
+                rd[j] = pre;
+                if (!tmp) {
+                    // the (4096 q + 1)-th one lies in block j iff pre < 4096 q + 1 <= pre + v
+                    const uint64_t q1 = ((uint64_t)pre + WT_SEL_SPACING - 1) / WT_SEL_SPACING;
+                    if (q1 * WT_SEL_SPACING < (uint64_t)pre + v[r]) s1[q1] = (uint32_t)j;
+                    const uint64_t bstart = j * 512;
+                    const uint64_t valid = bstart >= d.n ? 0 : min((uint64_t)512, d.n - bstart);
+                    const uint64_t zpre = min(bstart, d.n) - pre;
+                    const uint64_t zc = valid - v[r];
+                    const uint64_t q0 = (zpre + WT_SEL_SPACING - 1) / WT_SEL_SPACING;
+                    if (q0 * WT_SEL_SPACING < zpre + zc) s0[q0] = (uint32_t)j;
+                }
+            }
+            pre += v[r];
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace wtg
+
+namespace wtg {
+
+hipError_t launch_dirs(const TextDesc *d_descs, const uint32_t *bases, uint32_t nd, uint32_t nitems,
+                       uint32_t max_levels, bool tmp, uint32_t grid_cap, const LaunchCtx &ctx)
+{
+    if (max_levels == 0) return hipSuccess;
+    if (nitems) {
+        uint32_t grid = (grid_cap && nitems > grid_cap) ? grid_cap : nitems;
+        hipLaunchKernelGGL(k_dir_count, dim3(grid), dim3(256), 0, ctx.stream, d_descs, bases, nd,
+                           nitems, (uint32_t)tmp);
+        if (ctx.after) ctx.after(ctx.user, KID_DIR_COUNT);
+    }
+    hipLaunchKernelGGL(k_dir_scan, dim3(nd, max_levels), dim3(1024), 0, ctx.stream, d_descs, nd,
+                       (uint32_t)tmp);
+    if (ctx.after) ctx.after(ctx.user, KID_DIR_SCAN);
+    if (nitems) {
+        uint32_t grid = (grid_cap && nitems > grid_cap) ? grid_cap : nitems;
+        hipLaunchKernelGGL(k_dir_write, dim3(grid), dim3(256), 0, ctx.stream, d_descs, bases, nd,
+                           nitems, (uint32_t)tmp);
+        if (ctx.after) ctx.after(ctx.user, KID_DIR_WRITE);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace wtg

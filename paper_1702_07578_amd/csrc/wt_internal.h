@@ -1,0 +1,138 @@
+// Internal declarations of the GPU library: per-text build descriptor, plan
+// of the workspace, constants and the kernel launchers shared between the
+// translation units.  Not part of the public ABI (include/wt.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/wt.h"
+
+namespace wtg {
+
+// Tile kernels run 512 threads (8 wave64s).
+constexpr uint32_t kTileThreads = 512;
+constexpr uint32_t kTileWaves = kTileThreads / 64;
+// Bytes of one LDS element buffer of the scatter kernel: tiles hold
+// (32 KiB / sym_bytes) symbols.
+constexpr uint32_t kTileBufBytes = 32768;
+// Largest number of levels handled by one pass over the (re-ordered) text.
+constexpr uint32_t kMaxGroupBits = 8;
+// Directory: 512-bit blocks, chunks of kDirChunk blocks per workgroup.
+constexpr uint32_t kDirChunk = 1024;
+
+// Everything a kernel needs to know about one text of a build.  Lives in the
+// workspace (device memory); one entry per text of a batch.
+struct TextDesc {
+    // input
+    const void *text;
+    uint64_t n;
+    uint32_t b;     // bytes per symbol (1, 2, 4)
+    uint32_t L;     // levels
+    uint32_t kind;  // WT_TREE / WT_MATRIX
+    uint32_t K;     // levels per group (pass over the text)
+    uint32_t G;     // number of groups
+    uint32_t log2S; // log2 symbols per tile
+    uint32_t ntiles;
+    uint32_t tile_base; // first global work item of this text
+    uint32_t CH;        // tiles per chunk (column scan)
+    uint32_t nchunks;
+    uint32_t dir_chunks; // directory chunks per level
+    uint32_t pad0;
+    uint64_t W;  // words per level
+    uint64_t nb; // 512-bit blocks per level (W / 8)
+    uint64_t rank_stride, sel_stride;
+    // outputs
+    uint64_t *bits;
+    uint64_t *zeros;
+    uint32_t *rank_dir;
+    uint32_t *sel0, *sel1;
+    int32_t *status;
+    // workspace
+    uint32_t *H;   // [ntiles][2^K] per-tile histogram of the group key
+    uint32_t *TP;  // [ntiles][2^K] tile-exclusive prefix of H per key
+    uint32_t *CS;  // [nchunks][2^K] chunk sums -> chunk-exclusive prefixes
+    uint32_t *KBid, *KBpi; // [2^(K+1)] key bases per group level, prefix / reversed order
+    uint32_t *HT;  // [2^(K+1)] per group level key totals
+    void *seqA, *seqB;     // reordered text between groups (n symbols each)
+    uint64_t *tmp_bits;    // WT only, G > 1: WM levels K..L-1, [L-K][W]
+    uint32_t *tmp_rank;    // [L-K][rank_stride]
+    uint32_t *walk;        // WT only, G > 1: per level l in [K,L): 3 x 2^l u32
+    uint16_t *dir_bc;      // [Lall][nb] ones per 512-bit block
+    uint32_t *dir_cs;      // [Lall][dir_chunks] chunk sums -> prefixes
+};
+
+// Host-side plan of one text: the descriptor plus workspace size.
+struct Plan {
+    TextDesc d;
+    size_t ws_bytes;  // bytes of workspace used by this text (excluding descriptor)
+};
+
+// level a of a group: number of keys 2^a, table offset 2^a - 1
+__host__ __device__ inline uint32_t lvl_off(uint32_t a) { return (1u << a) - 1u; }
+
+__host__ __device__ inline uint32_t group_bits(const TextDesc &d, uint32_t g)
+{
+    uint32_t done = g * d.K;
+    if (done >= d.L) return 0;
+    uint32_t r = d.L - done;
+    return r < d.K ? r : d.K;
+}
+
+// walk table of level l (WT deep levels): wm_start, len, wt_start
+__host__ __device__ inline uint64_t walk_off(uint32_t K, uint32_t l)
+{
+    // sum over k in [K, l) of 3 * 2^k
+    return 3ull * ((1ull << l) - (1ull << K));
+}
+
+// kernel ids for profiling
+enum KernelId : uint32_t {
+    KID_INIT = 0,
+    KID_HIST,
+    KID_CHUNK_SUM,
+    KID_KEY_SCAN,
+    KID_TILE_PREFIX,
+    KID_ZERO_BORDERS,
+    KID_SCATTER,
+    KID_DIR_COUNT,
+    KID_DIR_SCAN,
+    KID_DIR_WRITE,
+    KID_WALK,
+    KID_GATHER,
+    KID_QUERY,
+    KID_COUNT_
+};
+
+// Launch hook: called after every kernel launch (profiling); may be null.
+struct LaunchCtx {
+    hipStream_t stream;
+    void (*after)(void *user, uint32_t kid);
+    void *user;
+};
+
+// Launchers (wt_build.hip, wt_dir.hip, wt_query.hip)
+struct GroupLaunch {
+    uint32_t g;
+    uint32_t nd;
+    const uint32_t *tile_bases;  // device, nd + 1 entries (unused when nd == 1)
+    const uint32_t *chunk_bases;
+    uint32_t ntiles;   // total tile items of the launch
+    uint32_t nchunks;  // total chunk items
+    bool any_levels;   // some text has at least one level in this group
+    uint32_t grid_cap; // 0: one workgroup per item
+};
+
+hipError_t launch_init(const TextDesc &d, TextDesc *d_dst, const LaunchCtx &ctx);
+hipError_t launch_init_batch(const TextDesc *d_descs, uint32_t nd, const LaunchCtx &ctx);
+hipError_t launch_group(const TextDesc *d_descs, const GroupLaunch &gl, const LaunchCtx &ctx);
+hipError_t launch_walk(const TextDesc *d_descs, const uint32_t *bases, uint32_t nd,
+                       uint32_t nitems, uint32_t step, const LaunchCtx &ctx);
+hipError_t launch_gather(const TextDesc *d_descs, const uint32_t *bases, uint32_t nd,
+                         uint32_t nitems, const LaunchCtx &ctx);
+hipError_t launch_dirs(const TextDesc *d_descs, const uint32_t *bases, uint32_t nd, uint32_t nitems,
+                       uint32_t max_levels, bool tmp, uint32_t grid_cap, const LaunchCtx &ctx);
+hipError_t launch_queries(const wt_levels &s, int op, const uint32_t *d_sym, const uint64_t *d_arg,
+                          uint64_t m, void *d_out, const LaunchCtx &ctx);
+
+}  // namespace wtg
