@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""Benchmark: wavelet tree + wavelet matrix construction on one MI355X.
+
+Workload: the text-like plain build, n = 2^30 uint8 symbols over sigma = 96
+(7 levels) from the seeded order-2 Markov recipe (see paper_1702_07578_amd/
+inputs).  One step = one wavelet-tree build plus one wavelet-matrix build of
+that text, each with its levels, Z and rank/select directories, inputs already
+resident in HBM.  value = 2 n / step time (symbols built per second, counted
+once per structure).
+
+Per-kernel durations come from HIP events recorded by the library after every
+kernel launch, on the build stream, inside the timed region.  The roofline
+object reports the dominant kernel (the stable scatter) against the HBM peak
+with its algorithmic bytes: the text re-read (n b) plus every level written
+once (L W 8).  The oracle (plain C, one thread) is timed on a bounded prefix of
+the same text as the CPU baseline.
+
+    python bench.py [--gpus 1] [--steps 10] [--warmup 3]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+COUNTERS = os.path.join(ROOT, "profiles", "scatter_markov96_counters.json")
+SCATTER_SRC = os.path.join(ROOT, "paper_1702_07578_amd", "csrc", "wt_build.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def scatter_traffic(per_launch_alg_bytes):
+    """HBM bytes per scatter launch from the committed counter runs, or None
+    when there are none or the kernel source changed since they were taken."""
+    if not os.path.exists(COUNTERS):
+        return None
+    c = json.load(open(COUNTERS))
+    src = hashlib.sha256(open(SCATTER_SRC, "rb").read()).hexdigest()
+    if c.get("source_sha256") != src:
+        return None
+    return c.get("bytes_per_launch")
+
+
+def cpu_baseline(text, L, sample_n):
+    import oracle
+    orc = oracle.load()
+    s = text[:sample_n]
+    t0 = time.perf_counter()
+    orc.build(1, s, L)
+    orc.build(0, s, L)
+    dt = time.perf_counter() - t0
+    return {"value": 2 * sample_n / dt, "unit": "symbols/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {sample_n} symbols of the same text, one WM and one WT build "
+                      f"(levels and Z) in {dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="markov96")
+    ap.add_argument("--n", type=int, default=0, help="override the text length")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 26)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tile-log2", type=int, default=0)
+    ap.add_argument("--group-bits", type=int, default=0)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has no "
+              "multi-GPU path. Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1702_07578_amd import binding as B
+    from paper_1702_07578_amd import inputs
+
+    t0 = time.time()
+    text, L = inputs.make(args.workload, args.n or None)
+    n = text.size
+    b = text.dtype.itemsize
+    log(f"generated {args.workload}: n={n} b={b} L={L} in {time.time() - t0:.1f}s")
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    d_text = B.to_device(text, dev)
+    tune = B.make_tune(tile_log2=args.tile_log2, group_bits=args.group_bits)
+    structs = {k: B.Structure(n, L, k, device=dev) for k in (B.WT_TREE, B.WT_MATRIX)}
+    ws_bytes = max(B.workspace_bytes(n, b, L, k, tune) for k in structs)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+
+    def step(rec=None):
+        for k in (B.WT_TREE, B.WT_MATRIX):
+            if rec is None:
+                B.build(d_text, n, b, L, k, tune=tune, ws=ws, out=structs[k])
+            else:
+                rec.build(d_text, n, b, L, k, structs[k], ws, tune=tune)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    for k, s in structs.items():
+        st = s.status()
+        if st != 0:
+            raise SystemExit(f"build status {st} for kind {k}")
+
+    # launches per step, to size the event pool
+    probe = B.EventRecorder(512)
+    start_probe = torch.cuda.Event(enable_timing=True)
+    start_probe.record()
+    step(probe)
+    torch.cuda.synchronize()
+    per_step = probe.used
+    rec = B.EventRecorder(per_step * args.steps + 8)
+
+    # ---- timed region ----
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step(rec)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = ev0.elapsed_time(ev1)
+    # ---- end timed region ----
+
+    ms_per_step = total_ms / args.steps
+    value = 2 * n / (ms_per_step / 1e3)
+    kt = rec.kernel_times(ev0)
+    kernels = {name: {"launches": len(v), "avg_ms": sum(v) / len(v), "total_ms_per_step": sum(v) / args.steps}
+               for name, v in kt.items()}
+    dom = max(kernels, key=lambda k: kernels[k]["total_ms_per_step"])
+
+    # algorithmic bytes per scatter launch: one launch per build here (one group)
+    W = structs[0].view.words_per_level
+    G = -(-L // 8) if L else 1
+    scat = kernels.get("scatter", {"avg_ms": float("nan"), "launches": 0})
+    per_launch_bytes = (n * b + L * W * 8) / max(1, G)
+    achieved = per_launch_bytes / (scat["avg_ms"] / 1e3) / 1e9
+    roofline = {"kernel": "scatter", "bound": "hbm", "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": scatter_traffic(per_launch_bytes),
+                "alg_bytes_per_launch": int(per_launch_bytes), "avg_launch_ms": round(scat["avg_ms"], 4)}
+    # whole-build roofline: B_alg = 2 n b + L W 8 + directories, per build
+    nb = W // 8
+    dir_bytes = L * (nb + 1) * 4 + 2 * L * ((n + 4095) // 4096 + 1) * 4
+    b_alg_build = 2 * n * b + L * W * 8 + dir_bytes
+    build_gbs = 2 * b_alg_build / (ms_per_step / 1e3) / 1e9
+
+    # correctness property on the measured outputs: access reconstructs the text
+    pos = torch.from_numpy(inputs.u64(1 << 16, n, 99, 0).view(np.int64)).to(dev)
+    want = torch.from_numpy(text.astype(np.uint32).view(np.int32)).to(dev)[pos]
+    for k, s in structs.items():
+        got = s.access(pos)
+        if not torch.equal(got, want):
+            raise SystemExit(f"access check failed for kind {k}")
+
+    # query throughput (extra): 2^20 access / rank / select on each structure
+    m = 1 << 20
+    qpos = torch.from_numpy(inputs.u64(m, n, 98, 1).view(np.int64)).to(dev)
+    qsym = torch.from_numpy(text[inputs.u64(m, n, 97, 2).astype(np.int64)].astype(np.uint32).view(np.int32)).to(dev)
+    qk = torch.ones(m, dtype=torch.int64, device=dev)
+    qe0, qe1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    qe0.record(stream)
+    for s in structs.values():
+        s.access(qpos)
+        s.rank(qsym, qpos)
+        s.select(qsym, qk)
+    qe1.record(stream)
+    torch.cuda.synchronize()
+    q_per_s = 6 * m / (qe0.elapsed_time(qe1) / 1e3)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(text, L, min(args.cpu_sample, n))
+
+    log(f"step {ms_per_step:.3f} ms; kernels per step: " +
+        ", ".join(f"{k} {v['total_ms_per_step']:.3f}ms" for k, v in sorted(kernels.items(), key=lambda x: -x[1]['total_ms_per_step'])))
+    out = {
+        "metric": "WT+WM build throughput (symbols/s), one GPU",
+        "value": round(value, 1),
+        "unit": "symbols/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: order-2 Markov text, n={n} uint8 symbols, sigma=96, "
+                               f"{L} levels; step = WT build + WM build (levels, Z, rank/select directories)",
+                   "n": n, "sym_bytes": b, "lg_sigma": L, "tile_log2": args.tile_log2 or "auto",
+                   "group_bits": args.group_bits or "auto"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "build_alg_gbs": round(build_gbs, 1),
+        "build_alg_frac": round(build_gbs / HBM_PEAK_GBS, 4),
+        "kernels": {k: {"avg_ms": round(v["avg_ms"], 4), "launches_per_step": v["launches"] // args.steps}
+                    for k, v in kernels.items()},
+        "dominant_kernel": dom,
+        "queries_per_s": round(q_per_s, 1),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -93,7 +93,7 @@ typedef struct wt_levels {
 typedef struct wt_tune {
     uint32_t tile_log2;  /* log2 of symbols per tile, 10..16 */
     uint32_t group_bits; /* levels handled per pass over the text, 1..8 */
-    uint32_t grid;       /* workgroups of the tile kernels (0: one per tile) */
+    uint32_t grid;       /* ranges of consecutive tiles per text, one workgroup each (0: 512) */
     uint32_t reserved;
 } wt_tune;
 
@@ -173,6 +173,21 @@ typedef struct wt_batch_item {
 size_t wt_batch_workspace_bytes(const wt_batch_item *items, uint32_t count, const wt_tune *tune);
 int wt_batch_build(const wt_batch_item *items, uint32_t count, void *d_ws, size_t ws_bytes,
                    const wt_tune *tune, hipStream_t stream);
+
+/*
+ * Timing aid: enqueue one build exactly like wt_build_tuned and, after every
+ * kernel launch i (i < capacity), record the caller's event events[i] on
+ * `stream` and store the launch's kernel id (see wt_kernel_name) in
+ * kernel_ids[i].  *recorded receives the number of launches (which may exceed
+ * capacity; launches past capacity are not recorded).  Asynchronous: the
+ * caller records a start event before the call and synchronises before
+ * reading elapsed times.  The events must be created by the caller
+ * (hipEventCreate, timing enabled).
+ */
+int wt_build_recorded(wt_kind kind, const void *d_text, uint64_t n, uint32_t sym_bytes,
+                      uint32_t lg_sigma, wt_levels *out, void *d_ws, size_t ws_bytes,
+                      const wt_tune *tune, hipStream_t stream, hipEvent_t *events,
+                      uint32_t *kernel_ids, uint32_t capacity, uint32_t *recorded);
 
 /*
  * Profiling aid: run one build like wt_build_tuned, recording a HIP event

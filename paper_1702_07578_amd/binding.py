@@ -7,7 +7,8 @@ this module fails loudly when the library has not been built.
 Names follow the C ABI: ``wt_output_bytes``, ``wt_workspace_bytes``,
 ``wt_levels_bind``, ``wt_build``, ``wm_build``, ``wt_build_tuned``,
 ``wt_access``, ``wt_rank``, ``wt_select``, ``wt_get_status``,
-``wt_batch_workspace_bytes``, ``wt_batch_build``, ``wt_build_profiled``.
+``wt_batch_workspace_bytes``, ``wt_batch_build``, ``wt_build_profiled``,
+``wt_build_recorded``.
 On top of them, ``Structure`` owns the torch buffers of one built index.
 """
 from __future__ import annotations
@@ -81,6 +82,9 @@ _SIGS = {
     "wt_build_profiled": (_i, [_i, _v, _u64, _u32, _u32, _LP, _v, _sz, _TP, _v,
                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint32), _u32]),
     "wt_kernel_name": (ctypes.c_char_p, [_u32]),
+    "wt_build_recorded": (_i, [_i, _v, _u64, _u32, _u32, _LP, _v, _sz, _TP, _v,
+                               ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_uint32),
+                               _u32, ctypes.POINTER(ctypes.c_uint32)]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(lib, _name)
@@ -274,3 +278,51 @@ def batch_build(items, tune=None, stream=None, ws=None):
     check(wt_batch_build(arr, len(items), ctypes.c_void_p(ws.data_ptr()), ws.numel(), _tune_ptr(tune),
                          _stream_handle(stream)), "wt_batch_build")
     return ws
+
+
+class EventRecorder:
+    """Caller-owned timing events for wt_build_recorded (torch events with
+    timing enabled; their raw handles are passed to the library)."""
+
+    def __init__(self, capacity: int):
+        torch = _torch()
+        self.events = [torch.cuda.Event(enable_timing=True) for _ in range(capacity)]
+        for e in self.events:  # instantiate the underlying HIP events
+            e.record()
+        torch.cuda.synchronize()
+        self.handles = (ctypes.c_void_p * capacity)(*[e.cuda_event for e in self.events])
+        self.ids = (ctypes.c_uint32 * capacity)()
+        self.capacity = capacity
+        self.used = 0
+
+    def build(self, d_text, n, sym_bytes, L, kind, structure, ws, tune=None, stream=None):
+        """Enqueue one build, recording an event after each kernel."""
+        rec = ctypes.c_uint32(0)
+        cap = self.capacity - self.used
+        if cap <= 0:
+            raise WtError(WT_ENOSPACE, "EventRecorder full")
+        hp = ctypes.cast(ctypes.byref(self.handles, self.used * ctypes.sizeof(ctypes.c_void_p)),
+                         ctypes.POINTER(ctypes.c_void_p))
+        ip = ctypes.cast(ctypes.byref(self.ids, self.used * 4), ctypes.POINTER(ctypes.c_uint32))
+        ptr = ctypes.c_void_p(d_text.data_ptr()) if n > 0 else ctypes.c_void_p(ws.data_ptr())
+        check(wt_build_recorded(kind, ptr, n, sym_bytes, L, ctypes.byref(structure.view),
+                                ctypes.c_void_p(ws.data_ptr()), ws.numel(), _tune_ptr(tune),
+                                _stream_handle(stream), hp, ip, cap, ctypes.byref(rec)),
+              "wt_build_recorded")
+        if rec.value > cap:
+            raise WtError(WT_ENOSPACE, "EventRecorder capacity exceeded")
+        first = self.used
+        self.used += rec.value
+        return first, self.used
+
+    def kernel_times(self, start_event, first=0, last=None):
+        """{kernel name: [ms of each launch]} for recorded launches [first, last);
+        the launch before `first` (or start_event) marks the start."""
+        last = self.used if last is None else last
+        out = {}
+        prev = start_event if first == 0 else self.events[first - 1]
+        for i in range(first, last):
+            name = wt_kernel_name(self.ids[i]).decode()
+            out.setdefault(name, []).append(prev.elapsed_time(self.events[i]))
+            prev = self.events[i]
+        return out

@@ -100,10 +100,14 @@ static int plan_text(uint64_t n, uint32_t b, uint32_t L, uint32_t kind, const wt
     ls = std::min(std::max(ls, 10u), smax);
     d.log2S = ls;
     d.ntiles = (uint32_t)cdiv64(n, 1ull << ls);
+    // consecutive tiles form a range, walked in order by one workgroup
+    const uint32_t target = (tune && tune->grid) ? tune->grid : kTargetRanges;
+    d.R = (uint32_t)std::max<uint64_t>(1, cdiv64(d.ntiles, target));
+    d.nranges = (uint32_t)cdiv64(d.ntiles, d.R);
     uint32_t ch = 1;
-    while ((uint64_t)ch * ch < d.ntiles) ch <<= 1;
+    while ((uint64_t)ch * ch < d.nranges) ch <<= 1;
     d.CH = ch;
-    d.nchunks = (uint32_t)cdiv64(d.ntiles, ch);
+    d.nchunks = (uint32_t)cdiv64(d.nranges, ch);
     d.W = words_per_level(n);
     d.nb = d.W / 8;
     d.rank_stride = rank_stride(n);
@@ -118,8 +122,8 @@ static int plan_text(uint64_t n, uint32_t b, uint32_t L, uint32_t kind, const wt
         off = align_up(off + bytes, 256);
         return o;
     };
-    p.o_H = take((uint64_t)d.ntiles * nk * 4);
-    p.o_TP = take((uint64_t)d.ntiles * nk * 4);
+    p.o_H = take((uint64_t)d.nranges * nk * 4);
+    p.o_TP = take((uint64_t)d.nranges * nk * 4);
     p.o_CS = take((uint64_t)d.nchunks * nk * 4);
     p.o_KBid = take((2 * nk) * 4);
     p.o_KBpi = take((2 * nk) * 4);
@@ -180,13 +184,14 @@ static int check_out(const wt_levels *out, uint64_t n, uint32_t L, uint32_t kind
 struct Sched {
     uint32_t nd = 0;
     uint32_t gmax = 0;
-    uint32_t ntiles = 0, nchunks = 0;
+    uint32_t nranges = 0, nchunks = 0;
     std::vector<bool> any_levels;  // per group
+    uint32_t bmask = 0;            // symbol widths present
     uint32_t dir_items = 0, tmpdir_items = 0, max_levels = 0, max_tmp_levels = 0;
     std::vector<uint32_t> walk_items;  // per step
     uint32_t gather_items = 0;
     // host prefix arrays (nd + 1 each), only needed for nd > 1
-    std::vector<uint32_t> b_tiles, b_chunks, b_dir, b_tmpdir, b_gather;
+    std::vector<uint32_t> b_ranges, b_chunks, b_dir, b_tmpdir, b_gather;
     std::vector<std::vector<uint32_t>> b_walk;
 };
 
@@ -209,7 +214,7 @@ static int schedule(const std::vector<TextDesc> &ds, Sched &s)
     std::vector<uint64_t> aw(max_steps, 0);
     for (const TextDesc &d : ds) {
         const bool deep = (d.kind == WT_TREE && d.G > 1);
-        push(s.b_tiles, at, d.ntiles);
+        push(s.b_ranges, at, d.nranges);
         push(s.b_chunks, ac, d.nchunks);
         push(s.b_dir, adir, (uint64_t)d.L * d.dir_chunks);
         push(s.b_tmpdir, atmp, deep ? (uint64_t)(d.L - d.K) * d.dir_chunks : 0);
@@ -220,10 +225,11 @@ static int schedule(const std::vector<TextDesc> &ds, Sched &s)
         }
         for (uint32_t g = 0; g < d.G; g++)
             if (group_bits(d, g) > 0) s.any_levels[g] = true;
+        s.bmask |= (d.b == 1) ? 1u : (d.b == 2 ? 2u : 4u);
         s.max_levels = std::max(s.max_levels, d.L);
         if (deep) s.max_tmp_levels = std::max(s.max_tmp_levels, d.L - d.K);
     }
-    s.b_tiles.push_back((uint32_t)at);
+    s.b_ranges.push_back((uint32_t)at);
     s.b_chunks.push_back((uint32_t)ac);
     s.b_dir.push_back((uint32_t)adir);
     s.b_tmpdir.push_back((uint32_t)atmp);
@@ -233,7 +239,7 @@ static int schedule(const std::vector<TextDesc> &ds, Sched &s)
     if (at > lim || ac > lim || adir > lim || atmp > lim || aga > lim) return WT_ENOTSUP;
     for (uint64_t x : aw)
         if (x > lim) return WT_ENOTSUP;
-    s.ntiles = (uint32_t)at;
+    s.nranges = (uint32_t)at;
     s.nchunks = (uint32_t)ac;
     s.dir_items = (uint32_t)adir;
     s.tmpdir_items = (uint32_t)atmp;
@@ -244,7 +250,7 @@ static int schedule(const std::vector<TextDesc> &ds, Sched &s)
 
 // Device copies of the prefix arrays (batch only); all null for one text.
 struct DevBases {
-    const uint32_t *tiles = nullptr, *chunks = nullptr, *dir = nullptr, *tmpdir = nullptr,
+    const uint32_t *ranges = nullptr, *chunks = nullptr, *dir = nullptr, *tmpdir = nullptr,
                    *gather = nullptr;
     std::vector<const uint32_t *> walk;
 };
@@ -257,12 +263,13 @@ static hipError_t run_build(const TextDesc *d_descs, const Sched &s, const DevBa
         GroupLaunch gl;
         gl.g = g;
         gl.nd = s.nd;
-        gl.tile_bases = b.tiles;
+        gl.range_bases = b.ranges;
         gl.chunk_bases = b.chunks;
-        gl.ntiles = s.ntiles;
+        gl.nranges = s.nranges;
         gl.nchunks = s.nchunks;
         gl.any_levels = s.any_levels[g];
-        gl.grid_cap = grid_cap;
+        gl.bmask = s.bmask;
+        gl.grid_cap = 0;
         if ((e = launch_group(d_descs, gl, ctx)) != hipSuccess) return e;
     }
     if (s.max_tmp_levels) {
@@ -297,7 +304,6 @@ static int build_one(wt_kind kind, const void *d_text, uint64_t n, uint32_t sym_
     bind_ws(p, base + align_up(sizeof(TextDesc), 256));
     p.d.text = d_text;
     bind_out(p.d, *out);
-    p.d.tile_base = 0;
     std::vector<TextDesc> ds{p.d};
     Sched s;
     if ((rc = schedule(ds, s)) != WT_OK) return rc;
@@ -464,7 +470,6 @@ static int plan_batch(const wt_batch_item *items, uint32_t count, const wt_tune 
     bp.n_bases = nb;
     bp.o_texts = align_up(bp.o_bases + nb * 4, 256);
     bp.total = bp.o_texts + off_texts + 256;
-    for (uint32_t i = 0; i < count; i++) bp.plans[i].d.tile_base = s.b_tiles[i];
     // stash text offsets in the plan (reuse the bytes field as offset)
     for (uint32_t i = 0; i < count; i++) bp.plans[i].bytes = text_off[i];
     if (sched) *sched = std::move(s);
@@ -513,7 +518,7 @@ static int batch_build(const wt_batch_item *items, uint32_t count, void *d_ws, s
         k += v.size();
         return p;
     };
-    db.tiles = put(s.b_tiles);
+    db.ranges = put(s.b_ranges);
     db.chunks = put(s.b_chunks);
     db.dir = put(s.b_dir);
     db.tmpdir = put(s.b_tmpdir);
@@ -598,3 +603,40 @@ const char *wt_kernel_name(uint32_t id)
 }
 
 }  // extern "C"
+
+// ---- caller-event recording ----------------------------------------------------
+
+namespace {
+struct RecState {
+    hipStream_t stream;
+    hipEvent_t *events;
+    uint32_t *ids;
+    uint32_t cap;
+    uint32_t count;
+    bool failed;
+};
+
+void rec_after(void *user, uint32_t kid)
+{
+    RecState *r = (RecState *)user;
+    if (r->count < r->cap) {
+        if (hipEventRecord(r->events[r->count], r->stream) != hipSuccess) r->failed = true;
+        r->ids[r->count] = kid;
+    }
+    r->count++;
+}
+}  // namespace
+
+extern "C" int wt_build_recorded(wt_kind kind, const void *d_text, uint64_t n, uint32_t sym_bytes,
+                                 uint32_t lg_sigma, wt_levels *out, void *d_ws, size_t ws_bytes,
+                                 const wt_tune *tune, hipStream_t stream, hipEvent_t *events,
+                                 uint32_t *kernel_ids, uint32_t capacity, uint32_t *recorded)
+{
+    if ((capacity && (!events || !kernel_ids)) || !recorded) return WT_EINVAL;
+    RecState r{stream, events, kernel_ids, capacity, 0, false};
+    LaunchCtx ctx{stream, rec_after, &r};
+    int rc = build_one(kind, d_text, n, sym_bytes, lg_sigma, out, d_ws, ws_bytes, tune, ctx);
+    *recorded = r.count;
+    if (rc == WT_OK && r.failed) rc = WT_EHIP;
+    return rc;
+}

@@ -10,14 +10,17 @@
 
 namespace wtg {
 
-// Tile kernels run 512 threads (8 wave64s).
+// Tile kernels run 512 threads (8 wave64s).  A tile is cut into one slice
+// per wave; a range of consecutive tiles is walked by one workgroup.
 constexpr uint32_t kTileThreads = 512;
 constexpr uint32_t kTileWaves = kTileThreads / 64;
 // Bytes of one LDS element buffer of the scatter kernel: tiles hold
-// (32 KiB / sym_bytes) symbols.
-constexpr uint32_t kTileBufBytes = 32768;
+// (8 KiB / sym_bytes) symbols.
+constexpr uint32_t kTileBufBytes = 8192;
 // Largest number of levels handled by one pass over the (re-ordered) text.
 constexpr uint32_t kMaxGroupBits = 8;
+// Ranges per text when the text is long enough (two workgroups per CU on 256 CUs).
+constexpr uint32_t kTargetRanges = 512;
 // Directory: 512-bit blocks, chunks of kDirChunk blocks per workgroup.
 constexpr uint32_t kDirChunk = 1024;
 
@@ -34,11 +37,11 @@ struct TextDesc {
     uint32_t G;     // number of groups
     uint32_t log2S; // log2 symbols per tile
     uint32_t ntiles;
-    uint32_t tile_base; // first global work item of this text
-    uint32_t CH;        // tiles per chunk (column scan)
+    uint32_t R;          // tiles per range; one workgroup walks a range in order
+    uint32_t CH;         // ranges per chunk (column scan)
     uint32_t nchunks;
     uint32_t dir_chunks; // directory chunks per level
-    uint32_t pad0;
+    uint32_t nranges;
     uint64_t W;  // words per level
     uint64_t nb; // 512-bit blocks per level (W / 8)
     uint64_t rank_stride, sel_stride;
@@ -49,8 +52,8 @@ struct TextDesc {
     uint32_t *sel0, *sel1;
     int32_t *status;
     // workspace
-    uint32_t *H;   // [ntiles][2^K] per-tile histogram of the group key
-    uint32_t *TP;  // [ntiles][2^K] tile-exclusive prefix of H per key
+    uint32_t *H;   // [nranges][2^K] per-range histogram of the group key
+    uint32_t *TP;  // [nranges][2^K] range-exclusive prefix of H per key
     uint32_t *CS;  // [nchunks][2^K] chunk sums -> chunk-exclusive prefixes
     uint32_t *KBid, *KBpi; // [2^(K+1)] key bases per group level, prefix / reversed order
     uint32_t *HT;  // [2^(K+1)] per group level key totals
@@ -115,17 +118,19 @@ struct LaunchCtx {
 struct GroupLaunch {
     uint32_t g;
     uint32_t nd;
-    const uint32_t *tile_bases;  // device, nd + 1 entries (unused when nd == 1)
+    const uint32_t *range_bases;  // device, nd + 1 entries (unused when nd == 1)
     const uint32_t *chunk_bases;
-    uint32_t ntiles;   // total tile items of the launch
+    uint32_t nranges;  // total range items of the launch
     uint32_t nchunks;  // total chunk items
     bool any_levels;   // some text has at least one level in this group
+    uint32_t bmask;    // symbol widths present: bit 0 (1 byte), 1 (2 bytes), 2 (4 bytes)
     uint32_t grid_cap; // 0: one workgroup per item
 };
 
 hipError_t launch_init(const TextDesc &d, TextDesc *d_dst, const LaunchCtx &ctx);
 hipError_t launch_init_batch(const TextDesc *d_descs, uint32_t nd, const LaunchCtx &ctx);
 hipError_t launch_group(const TextDesc *d_descs, const GroupLaunch &gl, const LaunchCtx &ctx);
+hipError_t launch_scatter(const TextDesc *d_descs, const GroupLaunch &gl, const LaunchCtx &ctx);
 hipError_t launch_walk(const TextDesc *d_descs, const uint32_t *bases, uint32_t nd,
                        uint32_t nitems, uint32_t step, const LaunchCtx &ctx);
 hipError_t launch_gather(const TextDesc *d_descs, const uint32_t *bases, uint32_t nd,
