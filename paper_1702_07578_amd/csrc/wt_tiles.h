@@ -5,6 +5,8 @@
 //            levels, bit-reversed order otherwise; Section 3.2 and 5.1) plus
 //            the key's count in every earlier tile (merged upward, Algorithm 1)
 //   h[a][k]  the tile's count of key k on level a
+//   lo[a][k] start of key k in the tile ordered by its reversed a-bit key
+//            (Observation 2): keys in bit-reversed order
 //   wb[a][k] first output word of key k's run, counting the words of the
 //            tile's runs on level a in key order; words[a] the total
 #pragma once
@@ -18,6 +20,7 @@ constexpr uint32_t kTab = (2u << kMaxGroupBits);  // >= 2^(K+1) - 1 entries
 struct TileTabs {
     uint32_t h[kTab];
     uint32_t G[kTab];
+    uint32_t lo[kTab];  // start of key k inside the tile's order after a splits
     uint32_t wb[kTab];
     uint32_t words[kMaxGroupBits + 1];
 };
