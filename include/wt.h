@@ -94,7 +94,7 @@ typedef struct wt_tune {
     uint32_t tile_log2;  /* log2 of symbols per tile, 10..16 */
     uint32_t group_bits; /* levels handled per pass over the text, 1..8 */
     uint32_t grid;       /* ranges of consecutive tiles per text, one workgroup each (0: 512) */
-    uint32_t reserved;
+    uint32_t persist;    /* workgroups per launch, looping over all work items (0: one per item) */
 } wt_tune;
 
 /* Bytes of the output buffer for a text of length n over lg_sigma levels
@@ -155,10 +155,16 @@ const char *wt_strerror(int code);
 /*
  * Batched build: `count` independent texts, each with its own length, symbol
  * width, lg_sigma, kind and output view, built by one sequence of launches
- * whose tile kernels loop over the (text, tile) work items of every text.
+ * whose kernels loop over the work items of every text (with tune->persist
+ * set, a fixed number of workgroups loops over all items: a persistent grid).
  * d_ws: workspace of wt_batch_workspace_bytes(items, count, tune) bytes.
- * Per-text descriptors are copied into the workspace from host memory with a
- * synchronous copy before any kernel is enqueued.
+ *   wt_batch_prepare  writes the per-text descriptors and work-item tables
+ *                     into the workspace with a synchronous host-to-device
+ *                     copy (host call; waits for `stream`).
+ *   wt_batch_launch   enqueues the kernels only (no host copies, no memset):
+ *                     capturable in a HIP graph and replayable, provided the
+ *                     items and workspace are those of the last prepare.
+ *   wt_batch_build    prepare followed by launch.
  */
 typedef struct wt_batch_item {
     const void *d_text;
@@ -171,6 +177,10 @@ typedef struct wt_batch_item {
 } wt_batch_item;
 
 size_t wt_batch_workspace_bytes(const wt_batch_item *items, uint32_t count, const wt_tune *tune);
+int wt_batch_prepare(const wt_batch_item *items, uint32_t count, void *d_ws, size_t ws_bytes,
+                     const wt_tune *tune, hipStream_t stream);
+int wt_batch_launch(const wt_batch_item *items, uint32_t count, void *d_ws, size_t ws_bytes,
+                    const wt_tune *tune, hipStream_t stream);
 int wt_batch_build(const wt_batch_item *items, uint32_t count, void *d_ws, size_t ws_bytes,
                    const wt_tune *tune, hipStream_t stream);
 

@@ -51,7 +51,7 @@ class WtLevels(ctypes.Structure):
 
 class WtTune(ctypes.Structure):
     _fields_ = [("tile_log2", ctypes.c_uint32), ("group_bits", ctypes.c_uint32),
-                ("grid", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("grid", ctypes.c_uint32), ("persist", ctypes.c_uint32)]
 
 
 class WtBatchItem(ctypes.Structure):
@@ -79,6 +79,8 @@ _SIGS = {
     "wt_strerror": (ctypes.c_char_p, [_i]),
     "wt_batch_workspace_bytes": (_sz, [ctypes.POINTER(WtBatchItem), _u32, _TP]),
     "wt_batch_build": (_i, [ctypes.POINTER(WtBatchItem), _u32, _v, _sz, _TP, _v]),
+    "wt_batch_prepare": (_i, [ctypes.POINTER(WtBatchItem), _u32, _v, _sz, _TP, _v]),
+    "wt_batch_launch": (_i, [ctypes.POINTER(WtBatchItem), _u32, _v, _sz, _TP, _v]),
     "wt_build_profiled": (_i, [_i, _v, _u64, _u32, _u32, _LP, _v, _sz, _TP, _v,
                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint32), _u32]),
     "wt_kernel_name": (ctypes.c_char_p, [_u32]),
@@ -116,10 +118,10 @@ def _stream_handle(stream=None):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def make_tune(tile_log2=0, group_bits=0, grid=0):
-    if not (tile_log2 or group_bits or grid):
+def make_tune(tile_log2=0, group_bits=0, grid=0, persist=0):
+    if not (tile_log2 or group_bits or grid or persist):
         return None
-    return WtTune(tile_log2, group_bits, grid, 0)
+    return WtTune(tile_log2, group_bits, grid, persist)
 
 
 def _tune_ptr(tune):
@@ -262,22 +264,46 @@ def build_profiled(d_text, n, sym_bytes, L, kind, tune=None, stream=None, ws=Non
     return s, res
 
 
+class Batch:
+    """A batch of texts bound to one workspace: prepare() uploads the
+    descriptors (host call), launch() enqueues the kernels only (capturable in
+    a graph), build() does both.  items: list of (d_text, n, sym_bytes, L,
+    kind, Structure)."""
+
+    def __init__(self, items, tune=None, ws=None):
+        torch = _torch()
+        self.items = items
+        self.tune = tune
+        self.arr = (WtBatchItem * len(items))()
+        for i, (t, n, b, L, kind, s) in enumerate(items):
+            self.arr[i] = WtBatchItem(ctypes.c_void_p(t.data_ptr() if n > 0 else s.buf.data_ptr()), n, b,
+                                      L, kind, 0, ctypes.pointer(s.view))
+        need = int(wt_batch_workspace_bytes(self.arr, len(items), _tune_ptr(tune)))
+        if need == 0:
+            raise WtError(WT_EINVAL, "wt_batch_workspace_bytes")
+        dev = items[0][5].buf.device
+        self.ws = ws if (ws is not None and ws.numel() >= need) else torch.empty(need, dtype=torch.uint8,
+                                                                                 device=dev)
+
+    def _args(self, stream):
+        return (self.arr, len(self.items), ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(),
+                _tune_ptr(self.tune), _stream_handle(stream))
+
+    def prepare(self, stream=None):
+        check(wt_batch_prepare(*self._args(stream)), "wt_batch_prepare")
+
+    def launch(self, stream=None):
+        check(wt_batch_launch(*self._args(stream)), "wt_batch_launch")
+
+    def build(self, stream=None):
+        check(wt_batch_build(*self._args(stream)), "wt_batch_build")
+
+
 def batch_build(items, tune=None, stream=None, ws=None):
-    """items: list of (d_text, n, sym_bytes, L, kind, Structure)."""
-    torch = _torch()
-    arr = (WtBatchItem * len(items))()
-    for i, (t, n, b, L, kind, s) in enumerate(items):
-        arr[i] = WtBatchItem(ctypes.c_void_p(t.data_ptr() if n > 0 else s.buf.data_ptr()), n, b, L,
-                             kind, 0, ctypes.pointer(s.view))
-    need = int(wt_batch_workspace_bytes(arr, len(items), _tune_ptr(tune)))
-    if need == 0:
-        raise WtError(WT_EINVAL, "wt_batch_workspace_bytes")
-    dev = items[0][5].buf.device
-    if ws is None or ws.numel() < need:
-        ws = torch.empty(need, dtype=torch.uint8, device=dev)
-    check(wt_batch_build(arr, len(items), ctypes.c_void_p(ws.data_ptr()), ws.numel(), _tune_ptr(tune),
-                         _stream_handle(stream)), "wt_batch_build")
-    return ws
+    """items: list of (d_text, n, sym_bytes, L, kind, Structure); returns the Batch."""
+    b = Batch(items, tune=tune, ws=ws)
+    b.build(stream)
+    return b
 
 
 class EventRecorder:

@@ -269,7 +269,7 @@ static hipError_t run_build(const TextDesc *d_descs, const Sched &s, const DevBa
         gl.nchunks = s.nchunks;
         gl.any_levels = s.any_levels[g];
         gl.bmask = s.bmask;
-        gl.grid_cap = 0;
+        gl.grid_cap = grid_cap;
         if ((e = launch_group(d_descs, gl, ctx)) != hipSuccess) return e;
     }
     if (s.max_tmp_levels) {
@@ -310,7 +310,7 @@ static int build_one(wt_kind kind, const void *d_text, uint64_t n, uint32_t sym_
     if (launch_init(p.d, d_desc, ctx) != hipSuccess) return WT_EHIP;
     DevBases b;
     b.walk.assign(s.walk_items.size(), nullptr);
-    const uint32_t cap = tune ? tune->grid : 0;
+    const uint32_t cap = tune ? tune->persist : 0;
     if (run_build(d_desc, s, b, cap, ctx) != hipSuccess) return WT_EHIP;
     return WT_OK;
 }
@@ -483,12 +483,20 @@ size_t wt_batch_workspace_bytes(const wt_batch_item *items, uint32_t count, cons
     return bp.total;
 }
 
-static int batch_build(const wt_batch_item *items, uint32_t count, void *d_ws, size_t ws_bytes,
-                       const wt_tune *tune, const LaunchCtx &ctx)
+// Binds every text of the batch to the workspace and builds the host image
+// of descriptors and work-item prefix arrays (uploaded by prepare).
+struct BatchImage {
+    std::vector<uint8_t> img;
+    const TextDesc *d_descs;
+    DevBases db;
+    Sched s;
+};
+
+static int batch_image(const wt_batch_item *items, uint32_t count, void *d_ws, size_t ws_bytes,
+                       const wt_tune *tune, BatchImage &bi)
 {
     BatchPlan bp;
-    Sched s;
-    int rc = plan_batch(items, count, tune, bp, &s);
+    int rc = plan_batch(items, count, tune, bp, &bi.s);
     if (rc != WT_OK) return rc;
     if (!d_ws) return WT_EINVAL;
     if (ws_bytes < bp.total) return WT_ENOSPACE;
@@ -505,12 +513,10 @@ static int batch_build(const wt_batch_item *items, uint32_t count, void *d_ws, s
         bind_out(p.d, *it.out);
         ds[i] = p.d;
     }
-    // host image of descriptors + prefix arrays
-    std::vector<uint8_t> img(bp.o_texts);
-    std::memcpy(img.data() + bp.o_desc, ds.data(), count * sizeof(TextDesc));
-    uint32_t *bases = (uint32_t *)(img.data() + bp.o_bases);
+    bi.img.assign(bp.o_texts, 0);
+    std::memcpy(bi.img.data() + bp.o_desc, ds.data(), count * sizeof(TextDesc));
+    uint32_t *bases = (uint32_t *)(bi.img.data() + bp.o_bases);
     uint32_t *dbases = (uint32_t *)(base + bp.o_bases);
-    DevBases db;
     uint64_t k = 0;
     auto put = [&](const std::vector<uint32_t> &v) {
         std::memcpy(bases + k, v.data(), v.size() * 4);
@@ -518,27 +524,61 @@ static int batch_build(const wt_batch_item *items, uint32_t count, void *d_ws, s
         k += v.size();
         return p;
     };
-    db.ranges = put(s.b_ranges);
-    db.chunks = put(s.b_chunks);
-    db.dir = put(s.b_dir);
-    db.tmpdir = put(s.b_tmpdir);
-    db.gather = put(s.b_gather);
-    for (auto &w : s.b_walk) db.walk.push_back(put(w));
-    if (hipMemcpyAsync(base, img.data(), img.size(), hipMemcpyHostToDevice, ctx.stream) != hipSuccess)
-        return WT_EHIP;
-    if (hipStreamSynchronize(ctx.stream) != hipSuccess) return WT_EHIP;
-    const TextDesc *d_descs = (const TextDesc *)(base + bp.o_desc);
-    if (launch_init_batch(d_descs, count, ctx) != hipSuccess) return WT_EHIP;
-    const uint32_t cap = tune ? tune->grid : 0;
-    if (run_build(d_descs, s, db, cap, ctx) != hipSuccess) return WT_EHIP;
+    bi.db.ranges = put(bi.s.b_ranges);
+    bi.db.chunks = put(bi.s.b_chunks);
+    bi.db.dir = put(bi.s.b_dir);
+    bi.db.tmpdir = put(bi.s.b_tmpdir);
+    bi.db.gather = put(bi.s.b_gather);
+    for (auto &w : bi.s.b_walk) bi.db.walk.push_back(put(w));
+    bi.d_descs = (const TextDesc *)(base + bp.o_desc);
     return WT_OK;
+}
+
+static int batch_prepare(const wt_batch_item *items, uint32_t count, void *d_ws, size_t ws_bytes,
+                         const wt_tune *tune, hipStream_t stream)
+{
+    BatchImage bi;
+    int rc = batch_image(items, count, d_ws, ws_bytes, tune, bi);
+    if (rc != WT_OK) return rc;
+    uint8_t *base = (uint8_t *)align_up((uintptr_t)d_ws, 256);
+    if (hipStreamSynchronize(stream) != hipSuccess) return WT_EHIP;
+    if (hipMemcpy(base, bi.img.data(), bi.img.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return WT_EHIP;
+    return WT_OK;
+}
+
+static int batch_launch(const wt_batch_item *items, uint32_t count, void *d_ws, size_t ws_bytes,
+                        const wt_tune *tune, const LaunchCtx &ctx)
+{
+    BatchImage bi;
+    int rc = batch_image(items, count, d_ws, ws_bytes, tune, bi);
+    if (rc != WT_OK) return rc;
+    if (launch_init_batch(bi.d_descs, count, ctx) != hipSuccess) return WT_EHIP;
+    const uint32_t cap = tune ? tune->persist : 0;
+    if (run_build(bi.d_descs, bi.s, bi.db, cap, ctx) != hipSuccess) return WT_EHIP;
+    return WT_OK;
+}
+
+int wt_batch_prepare(const wt_batch_item *items, uint32_t count, void *d_ws, size_t ws_bytes,
+                     const wt_tune *tune, hipStream_t stream)
+{
+    return batch_prepare(items, count, d_ws, ws_bytes, tune, stream);
+}
+
+int wt_batch_launch(const wt_batch_item *items, uint32_t count, void *d_ws, size_t ws_bytes,
+                    const wt_tune *tune, hipStream_t stream)
+{
+    LaunchCtx ctx{stream, nullptr, nullptr};
+    return batch_launch(items, count, d_ws, ws_bytes, tune, ctx);
 }
 
 int wt_batch_build(const wt_batch_item *items, uint32_t count, void *d_ws, size_t ws_bytes,
                    const wt_tune *tune, hipStream_t stream)
 {
+    int rc = batch_prepare(items, count, d_ws, ws_bytes, tune, stream);
+    if (rc != WT_OK) return rc;
     LaunchCtx ctx{stream, nullptr, nullptr};
-    return batch_build(items, count, d_ws, ws_bytes, tune, ctx);
+    return batch_launch(items, count, d_ws, ws_bytes, tune, ctx);
 }
 
 // ---- profiling ---------------------------------------------------------------
