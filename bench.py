@@ -31,7 +31,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 COUNTERS = os.path.join(ROOT, "profiles", "scatter_markov96_counters.json")
-SCATTER_SRC = os.path.join(ROOT, "paper_1702_07578_amd", "csrc", "wt_build.hip")
+SCATTER_SRC = os.path.join(ROOT, "paper_1702_07578_amd", "csrc", "wt_scatter.hip")
 
 
 def log(*a):
@@ -74,6 +74,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile-log2", type=int, default=0)
     ap.add_argument("--group-bits", type=int, default=0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain elementwise copy of 1 GiB three times (the reference "
+                         "kernel for scaling the HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -96,6 +99,15 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
+    if args.calibrate_copy:
+        # bitwise_not reads 1 GiB and writes 1 GiB in one elementwise kernel
+        x = torch.zeros(1 << 28, dtype=torch.int32, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            torch.bitwise_not(x, out=y)
+        torch.cuda.synchronize()
+        del x, y
+        log("copy calibration: 3 x bitwise_not over 2^28 int32 (1 GiB read + 1 GiB write each)")
     d_text = B.to_device(text, dev)
     tune = B.make_tune(tile_log2=args.tile_log2, group_bits=args.group_bits)
     structs = {k: B.Structure(n, L, k, device=dev) for k in (B.WT_TREE, B.WT_MATRIX)}
