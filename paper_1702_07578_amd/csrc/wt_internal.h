@@ -10,17 +10,19 @@
 
 namespace wtg {
 
-// Tile kernels run 512 threads (8 wave64s).  A tile is cut into one slice
-// per wave; a range of consecutive tiles is walked by one workgroup.
+// Range kernels (histogram, border zeroing) run 512 threads (8 wave64s) per
+// range of consecutive tiles.
 constexpr uint32_t kTileThreads = 512;
 constexpr uint32_t kTileWaves = kTileThreads / 64;
-// Bytes of one LDS element buffer of the scatter kernel: tiles hold
-// (8 KiB / sym_bytes) symbols.
-constexpr uint32_t kTileBufBytes = 8192;
+// The scatter gives every wave a range of its own and walks it one tile at a
+// time; a tile is at most kWaveTile symbols (held in registers, 32 per lane).
+constexpr uint32_t kWaveTile = 2048;
+constexpr uint32_t kScatWaves = 4;  // waves per scatter workgroup
 // Largest number of levels handled by one pass over the (re-ordered) text.
 constexpr uint32_t kMaxGroupBits = 8;
-// Ranges per text when the text is long enough (two workgroups per CU on 256 CUs).
-constexpr uint32_t kTargetRanges = 512;
+// Ranges per text when the text is long enough: one per scatter wave, about
+// 32 waves per CU on 256 CUs.
+constexpr uint32_t kTargetRanges = 8192;
 // Directory: 512-bit blocks, chunks of kDirChunk blocks per workgroup.
 constexpr uint32_t kDirChunk = 1024;
 
@@ -37,7 +39,7 @@ struct TextDesc {
     uint32_t G;     // number of groups
     uint32_t log2S; // log2 symbols per tile
     uint32_t ntiles;
-    uint32_t R;          // tiles per range; one workgroup walks a range in order
+    uint32_t R;          // tiles per range; one scatter wave walks a range in order
     uint32_t CH;         // ranges per chunk (column scan)
     uint32_t nchunks;
     uint32_t dir_chunks; // directory chunks per level
