@@ -93,12 +93,9 @@ static int plan_text(uint64_t n, uint32_t b, uint32_t L, uint32_t kind, const wt
     if (L > 0 && K > L) K = L;
     d.K = K;
     d.G = (L == 0) ? 1 : (uint32_t)cdiv64(L, K);
-    const uint32_t smax = log2_floor(kWaveTile);
-    uint32_t ls;
-    if (tune && tune->tile_log2) ls = tune->tile_log2;
-    else ls = (uint32_t)std::max<int64_t>(10, (int64_t)log2_floor(n ? n : 1) - 8);
-    ls = std::min(std::max(ls, 10u), smax);
-    d.log2S = ls;
+    // tiles are always kWaveTile symbols (the scatter holds one in registers)
+    d.log2S = log2_floor(kWaveTile);
+    const uint32_t ls = d.log2S;
     d.ntiles = (uint32_t)cdiv64(n, 1ull << ls);
     // consecutive tiles form a range, walked in order by one workgroup
     const uint32_t target = (tune && tune->grid) ? tune->grid : kTargetRanges;

@@ -62,17 +62,53 @@ __device__ inline uint32_t mbcnt64(uint64_t mask)
 
 __device__ inline uint32_t lane_id() { return mbcnt64(~0ull); }
 
-// inclusive prefix sum over the 64 lanes of a wave
+// x of the lane k places below within its row of 16 lanes, 0 if there is
+// none (DPP row_shr:k); the whole wave must be active
+template <int K>
+__device__ inline uint32_t dpp_row_shr(uint32_t x)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x110 + K, 0xf, 0xf, false);
+}
+
+// lane 15 of the previous row in rows 1 and 3, else 0 (DPP row_bcast:15)
+__device__ inline uint32_t dpp_bcast15(uint32_t x)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);
+}
+
+// lane 31 in rows 2 and 3, else 0 (DPP row_bcast:31)
+__device__ inline uint32_t dpp_bcast31(uint32_t x)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);
+}
+
+// inclusive prefix sum over the 64 lanes of a wave (all lanes active):
+// within rows of 16 by shifted adds, then across rows by broadcasts
 __device__ inline uint32_t wave_incl_scan(uint32_t x)
 {
-    const uint32_t lane = lane_id();
-#pragma unroll
-    for (uint32_t off = 1; off < 64; off <<= 1) {
-        uint32_t y = __shfl_up(x, off, 64);
-        if (lane >= off) x += y;
-    }
+    x += dpp_row_shr<1>(x);
+    x += dpp_row_shr<2>(x);
+    x += dpp_row_shr<4>(x);
+    x += dpp_row_shr<8>(x);
+    x += dpp_bcast15(x);
+    x += dpp_bcast31(x);
     return x;
 }
+
+// inclusive prefix maximum over the 64 lanes of a wave (all lanes active)
+__device__ inline uint32_t wave_incl_max(uint32_t x)
+{
+    x = max(x, dpp_row_shr<1>(x));
+    x = max(x, dpp_row_shr<2>(x));
+    x = max(x, dpp_row_shr<4>(x));
+    x = max(x, dpp_row_shr<8>(x));
+    x = max(x, dpp_bcast15(x));
+    x = max(x, dpp_bcast31(x));
+    return x;
+}
+
+// value of lane 63
+__device__ inline uint32_t last_lane(uint32_t x) { return __builtin_amdgcn_readlane(x, 63); }
 
 // ones in bits[0, i) using the 512-bit block directory rd
 __device__ inline uint64_t rank1_dir(const uint64_t *__restrict__ bits, const uint32_t *__restrict__ rd,

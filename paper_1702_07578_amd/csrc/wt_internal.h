@@ -20,9 +20,9 @@ constexpr uint32_t kWaveTile = 2048;
 constexpr uint32_t kScatWaves = 4;  // waves per scatter workgroup
 // Largest number of levels handled by one pass over the (re-ordered) text.
 constexpr uint32_t kMaxGroupBits = 8;
-// Ranges per text when the text is long enough: one per scatter wave, about
-// 32 waves per CU on 256 CUs.
-constexpr uint32_t kTargetRanges = 8192;
+// Ranges per text when the text is long enough: four per resident scatter
+// wave (12 per CU on 256 CUs), so that the last round of ranges is short.
+constexpr uint32_t kTargetRanges = 12288;
 // Directory: 512-bit blocks, chunks of kDirChunk blocks per workgroup.
 constexpr uint32_t kDirChunk = 1024;
 

@@ -18,6 +18,8 @@
 // with another range are filled by atomic OR.  With more than one group, the
 // split by the group's last bit writes every symbol straight to its position
 // in the next group's sequence.
+#include <type_traits>
+
 #include "wt_tiles.h"
 
 namespace wtg {
@@ -54,18 +56,6 @@ __device__ inline void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// inclusive prefix maximum over the 64 lanes of a wave
-__device__ inline uint32_t wave_incl_max(uint32_t x)
-{
-    const uint32_t lane = lane_id();
-#pragma unroll
-    for (uint32_t off = 1; off < 64; off <<= 1) {
-        uint32_t y = __shfl_up(x, off, 64);
-        if (lane >= off) x = max(x, y);
-    }
-    return x;
-}
-
 // exclusive scan of n <= 64 PER values by one wave, PER consecutive values
 // per lane; get(i) / put(i, x); returns the total
 template <uint32_t PER, typename Get, typename Put>
@@ -88,7 +78,7 @@ __device__ inline uint32_t wave_exscan_n(uint32_t n, Get get, Put put)
         if (i < n) put(i, ex);
         ex += v[r];
     }
-    return __shfl(incl, 63, 64);
+    return last_lane(incl);
 }
 
 // level of table entry e (entries lvl_off(a) .. lvl_off(a+1)-1 are level a)
@@ -104,17 +94,27 @@ __device__ inline uint64_t stream_bits(const uint64_t *src, uint32_t s, uint32_t
     return x;
 }
 
-// acc_lo/acc_hi of lane c := the 64-bit wave-uniform value B
-__device__ inline void put_lane(uint32_t &acc_lo, uint32_t &acc_hi, uint64_t B, uint32_t c)
+// f(integral_constant<I>) for I = B .. N-1, unrolled at compile time
+template <uint32_t I, uint32_t N, typename F>
+__device__ __attribute__((always_inline)) inline void static_for(F &&f)
 {
-    asm volatile("s_mov_b32 m0, %2\n\tv_writelane_b32 %0, %1, m0"
-                 : "+v"(acc_lo)
-                 : "s"((uint32_t)B), "s"(c)
-                 : "m0");
-    asm volatile("s_mov_b32 m0, %2\n\tv_writelane_b32 %0, %1, m0"
-                 : "+v"(acc_hi)
-                 : "s"((uint32_t)(B >> 32)), "s"(c)
-                 : "m0");
+    if constexpr (I < N) {
+        f(std::integral_constant<uint32_t, I>{});
+        static_for<I + 1, N>(f);
+    }
+}
+
+// acc_lo/acc_hi of lane c := the 64-bit wave-uniform value B
+template <uint32_t c>
+__device__ inline void put_lane(uint32_t &acc_lo, uint32_t &acc_hi, uint64_t B)
+{
+    asm volatile(
+        "s_mov_b32 m0, %4\n\t"
+        "v_writelane_b32 %0, %2, m0\n\t"
+        "v_writelane_b32 %1, %3, m0"
+        : "+v"(acc_lo), "+v"(acc_hi)
+        : "s"((uint32_t)B), "s"((uint32_t)(B >> 32)), "n"(c)
+        : "m0");
 }
 
 // G at the first tile of range r: the range prefix of every finest key merged
@@ -150,7 +150,7 @@ __device__ inline uint32_t full_words(uint32_t gs, uint32_t hh)
 // plain stores: the full words of all runs are numbered run by run, and the
 // lanes take consecutive words.
 template <typename E>
-__device__ void copy_full_words(const TextDesc &d, uint32_t g, uint32_t Kg, WaveSmem<E> &sm)
+__device__ __attribute__((always_inline)) inline void copy_full_words(const TextDesc &d, uint32_t g, uint32_t Kg, WaveSmem<E> &sm)
 {
     const uint32_t lane = lane_id();
     const uint32_t nr = lvl_off(Kg);
@@ -170,8 +170,9 @@ __device__ void copy_full_words(const TextDesc &d, uint32_t g, uint32_t Kg, Wave
         const uint32_t q = lane * PER + i;
         if (q < total) m = max(m, (uint32_t)sm.kw[q]);
     }
-    uint32_t run = __shfl_up(wave_incl_max(m), 1, 64);
-    if (lane == 0) run = 0;
+    // carry: the maximum over the lanes below
+    uint32_t run = wave_incl_max(m);
+    run = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)run, 0x138, 0xf, 0xf, false);  // wave_shr:1
 #pragma unroll
     for (uint32_t i = 0; i < PER; i++) {
         const uint32_t q = lane * PER + i;
@@ -196,7 +197,7 @@ __device__ void copy_full_words(const TextDesc &d, uint32_t g, uint32_t Kg, Wave
 // with the word kept from earlier tiles of the range, stored when complete,
 // kept otherwise.
 template <typename E>
-__device__ void run_end_words(const TextDesc &d, uint32_t g, uint32_t Kg, WaveSmem<E> &sm)
+__device__ __attribute__((always_inline)) inline void run_end_words(const TextDesc &d, uint32_t g, uint32_t Kg, WaveSmem<E> &sm)
 {
     for (uint32_t e = lane_id(); e < lvl_off(Kg); e += 64) {
         const uint32_t hh = sm.h[e];
@@ -239,81 +240,108 @@ __device__ void run_end_words(const TextDesc &d, uint32_t g, uint32_t Kg, WaveSm
 // One split (or, MODE 2, only the ballots) of the tile by bit `bit`: the
 // ballots are level a in the current order; MODE 0 writes every symbol to
 // its place in the next order in LDS, MODE 1 to its place in the next
-// group's sequence (global).
-template <typename E, uint32_t NCH, bool FULL, int MODE>
-__device__ inline void split_pass(const TextDesc &d, uint32_t (&v)[NCH], uint32_t len, uint32_t a,
-                                  uint32_t bit, uint32_t shift, uint32_t Kg, E *gout,
-                                  WaveSmem<E> &sm)
+// group's sequence (global).  A tile shorter than kWaveTile is padded with
+// symbols whose bits are all one: they sort after every real symbol at every
+// level, so the real symbols keep their places and the padding fills the
+// end of every level's stream.
+template <typename E, int MODE>
+__device__ __attribute__((always_inline)) inline void split_pass(
+    const TextDesc &d, uint32_t (&v)[kChunks], bool padded, uint32_t a, uint32_t bit,
+    uint32_t shift, uint32_t Kg, E *gout, WaveSmem<E> &sm)
 {
     const uint32_t lane = lane_id();
-    const uint32_t nch = FULL ? NCH : (len + 63) >> 6;
     const uint32_t kmask = (1u << Kg) - 1u;
+    const uint32_t neg_lane = 0u - lane;
+    // LDS address of the element buffer
+    const uint32_t ebase = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) E *)sm.elem;
     uint32_t acc_lo = 0, acc_hi = 0;
     // the zeros of level a in the tile: the start of the first key whose bit
     // a is one, in the order of level a + 1
     uint32_t base0 = 0;
     uint32_t base1 = MODE == 2 ? 0u : __builtin_amdgcn_readfirstlane((uint32_t)sm.lo[lvl_off(a + 1) + 1]);
-#pragma unroll
-    for (uint32_t c = 0; c < NCH; c++) {
-        if (FULL || c < nch) {
-            const bool ok = FULL || c * 64 + lane < len;
-            const uint32_t x = v[c];
-            const bool one = ok && (x & bit) != 0;
-            const uint64_t B = __ballot(one);
-            put_lane(acc_lo, acc_hi, B, c);
-            if (MODE != 2) {
-                const uint32_t d1 = __builtin_amdgcn_mbcnt_hi(
-                    (uint32_t)(B >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)B, base1));
-                const uint32_t d0 = (base0 + base1) + lane - d1;
-                const uint32_t dst = one ? d1 : d0;
-                if (ok) {
-                    if (MODE == 0) {
-                        sm.elem[dst] = (E)x;
-                    } else {
-                        const uint32_t key = (x >> shift) & kmask;
-                        const uint32_t gi = sm.G[lvl_off(Kg) + key] + (dst - sm.lo[lvl_off(Kg) + key]);
-                        if (gi < d.n) gout[gi] = (E)x;
-                    }
-                }
-                const uint32_t ones = __popcll(B);
-                base0 += (FULL ? 64u : min(64u, len - c * 64)) - ones;
-                base1 += ones;
+    static_for<0, kChunks>([&](auto ci) {
+        constexpr uint32_t c = decltype(ci)::value;
+        const uint32_t x = v[c];
+        const bool one = (x & bit) != 0;
+        const uint64_t B = __ballot(one);
+        put_lane<c>(acc_lo, acc_hi, B);
+        if (MODE == 0) {
+            // m = (ones before this lane in the chunk) - lane; a one goes to
+            // base1 + m + lane, a zero to base0 - m.  The bases are kept
+            // opaque so that they stay scalar.
+            const uint32_t m = __builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(B >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)B, neg_lane));
+            const uint32_t s0 = ebase + base0 * (uint32_t)sizeof(E);
+            const uint32_t s1 = ebase + base1 * (uint32_t)sizeof(E);
+            const uint32_t i1 = s1 + (m + lane) * (uint32_t)sizeof(E);
+            const uint32_t i0 = s0 - m * (uint32_t)sizeof(E);
+            *(__attribute__((address_space(3))) E *)(uintptr_t)(one ? i1 : i0) = (E)x;
+        } else if (MODE == 1) {
+            const uint32_t r1 = mbcnt64(B);
+            const uint32_t dst = one ? base1 + r1 : base0 + (lane - r1);
+            const uint32_t e = lvl_off(Kg) + ((x >> shift) & kmask);
+            const uint32_t rank = dst - sm.lo[e];
+            // padding ranks past the key's count
+            if (!padded || rank < sm.h[e]) {
+                const uint32_t gi = sm.G[e] + rank;
+                if (gi < d.n) gout[gi] = (E)x;
             }
         }
-    }
-    if (lane < nch) sm.bits[a][lane] = ((uint64_t)acc_hi << 32) | acc_lo;
+        if (MODE != 2) {
+            const uint32_t ones = __popcll(B);
+            base0 += 64u - ones;
+            base1 += ones;
+            asm volatile("" : "+s"(base0), "+s"(base1));
+        }
+    });
+    if (lane < kChunks) sm.bits[a][lane] = ((uint64_t)acc_hi << 32) | acc_lo;
 }
 
-// One tile of NCH chunks.  FULL: the tile holds exactly 64 NCH symbols
-// (every tile but possibly the text's last one); otherwise the chunks past
-// the text's end are masked lane by lane.
-template <typename E, uint32_t NCH, bool FULL>
-__device__ void wave_tile(const TextDesc &d, uint32_t g, uint32_t Kg, uint32_t t, WaveSmem<E> &sm)
+// One tile of kWaveTile symbols (the text's last tile may be shorter; it is
+// padded).
+template <typename E>
+__device__ __attribute__((always_inline)) inline void wave_tile(const TextDesc &d, uint32_t g,
+                                                                uint32_t Kg, uint32_t t,
+                                                                WaveSmem<E> &sm)
 {
     const uint32_t lane = lane_id();
-    const uint64_t start = (uint64_t)t << d.log2S;
-    const uint32_t len = FULL ? NCH * 64 : (uint32_t)(d.n - start);
+    const uint64_t start = (uint64_t)t * kWaveTile;
+    const uint32_t len = (uint32_t)min((uint64_t)kWaveTile, d.n - start);
+    const bool padded = len < kWaveTile;
     const uint32_t shift = d.L - g * d.K - Kg;
     const uint32_t nk = 1u << Kg, kmask = nk - 1u;
     const bool reorder = (g + 1 < d.G);
     const E *src = (const E *)seq_in(d, g) + start + lane;
     uint32_t *h = sm.h;
-    // lane holds a symbol of chunk c
-    auto valid = [&](uint32_t c) { return FULL || c * 64 + lane < len; };
 
-    // 1. the tile into registers: chunk c, lane l holds symbol 64 c + l
-    uint32_t v[NCH];
-#pragma unroll
-    for (uint32_t c = 0; c < NCH; c++) v[c] = valid(c) ? (uint32_t)src[c * 64] : 0u;
-
-    // 2. the tile's count of every key: the finest level by LDS atomics, the
-    //    others as differences of the finest prefix sums P
+    // 1. the tile, in text order, through registers into LDS, counting the
+    //    finest keys by LDS atomics on the way (the registers are free while
+    //    the tables are built)
     for (uint32_t k = lane; k < nk; k += 64) h[lvl_off(Kg) + k] = 0;
     wave_sync();
+    {
+        uint32_t v[kChunks];
+        if (!padded) {
 #pragma unroll
-    for (uint32_t c = 0; c < NCH; c++)
-        if (valid(c)) atomicAdd(&h[lvl_off(Kg) + ((v[c] >> shift) & kmask)], 1u);
+            for (uint32_t c = 0; c < kChunks; c++) v[c] = src[c * 64];
+#pragma unroll
+            for (uint32_t c = 0; c < kChunks; c++)
+                atomicAdd(&h[lvl_off(Kg) + ((v[c] >> shift) & kmask)], 1u);
+        } else {
+#pragma unroll
+            for (uint32_t c = 0; c < kChunks; c++)
+                v[c] = (c * 64 + lane < len) ? (uint32_t)src[c * 64] : (uint32_t)(E)~0u;
+#pragma unroll
+            for (uint32_t c = 0; c < kChunks; c++)
+                if (c * 64 + lane < len) atomicAdd(&h[lvl_off(Kg) + ((v[c] >> shift) & kmask)], 1u);
+        }
+#pragma unroll
+        for (uint32_t c = 0; c < kChunks; c++) sm.elem[c * 64 + lane] = (E)v[c];
+    }
     wave_sync();
+
+    // 2. the tile's count of every key: the others as differences of the
+    //    finest prefix sums P (padding not counted)
     uint16_t *P = sm.kw;
     wave_exscan_n<4>(
         nk, [&](uint32_t k) { return h[lvl_off(Kg) + k]; },
@@ -342,17 +370,20 @@ __device__ void wave_tile(const TextDesc &d, uint32_t g, uint32_t Kg, uint32_t t
     wave_sync();
 
     // 4. split by one bit at a time; the ballots are the levels
+    uint32_t v[kChunks];
+#pragma unroll
+    for (uint32_t c = 0; c < kChunks; c++) v[c] = sm.elem[c * 64 + lane];
+    wave_sync();
     E *gout = (E *)seq_out(d, g);
     for (uint32_t a = 0; a + 1 < Kg; a++) {
-        split_pass<E, NCH, FULL, 0>(d, v, len, a, 1u << (shift + Kg - 1 - a), shift, Kg, gout, sm);
+        split_pass<E, 0>(d, v, padded, a, 1u << (shift + Kg - 1 - a), shift, Kg, gout, sm);
         wave_sync();
 #pragma unroll
-        for (uint32_t c = 0; c < NCH; c++)
-            if (valid(c)) v[c] = sm.elem[c * 64 + lane];
+        for (uint32_t c = 0; c < kChunks; c++) v[c] = sm.elem[c * 64 + lane];
         wave_sync();
     }
-    if (reorder) split_pass<E, NCH, FULL, 1>(d, v, len, Kg - 1, 1u << shift, shift, Kg, gout, sm);
-    else split_pass<E, NCH, FULL, 2>(d, v, len, Kg - 1, 1u << shift, shift, Kg, gout, sm);
+    if (reorder) split_pass<E, 1>(d, v, padded, Kg - 1, 1u << shift, shift, Kg, gout, sm);
+    else split_pass<E, 2>(d, v, padded, Kg - 1, 1u << shift, shift, Kg, gout, sm);
     wave_sync();
 
     // 5. every level's runs to their interval starts
@@ -372,11 +403,7 @@ __device__ void wave_range(const TextDesc &d, uint32_t g, uint32_t Kg, uint32_t 
     for (uint32_t e = lane; e < kRuns; e += 64) sm.pend_w[e] = kNoPend;
     wave_sync();
     const uint32_t t0 = r * d.R, t1 = min(d.ntiles, t0 + d.R);
-    for (uint32_t t = t0; t < t1; t++) {
-        if (((uint64_t)(t + 1) << d.log2S) > d.n) wave_tile<E, kChunks, false>(d, g, Kg, t, sm);
-        else if (d.log2S == 11) wave_tile<E, 32, true>(d, g, Kg, t, sm);
-        else wave_tile<E, 16, true>(d, g, Kg, t, sm);
-    }
+    for (uint32_t t = t0; t < t1; t++) wave_tile<E>(d, g, Kg, t, sm);
     // words still open at the end of the range are shared with the next one
     for (uint32_t e = lane; e < lvl_off(Kg); e += 64) {
         const uint32_t pw = sm.pend_w[e];
