@@ -183,6 +183,7 @@ struct Sched {
     uint32_t gmax = 0;
     uint32_t nranges = 0, nchunks = 0;
     std::vector<bool> any_levels;  // per group
+    std::vector<uint32_t> rmask;   // per group: bit 0 last group of a text, bit 1 not last
     uint32_t bmask = 0;            // symbol widths present
     uint32_t dir_items = 0, tmpdir_items = 0, max_levels = 0, max_tmp_levels = 0;
     std::vector<uint32_t> walk_items;  // per step
@@ -201,6 +202,7 @@ static int schedule(const std::vector<TextDesc> &ds, Sched &s)
         if (d.kind == WT_TREE && d.G > 1) max_steps = std::max(max_steps, d.L - d.K - 1);
     }
     s.any_levels.assign(s.gmax, false);
+    s.rmask.assign(s.gmax, 0u);
     s.walk_items.assign(max_steps, 0);
     s.b_walk.assign(max_steps, {});
     auto push = [](std::vector<uint32_t> &v, uint64_t &acc, uint64_t add) {
@@ -220,8 +222,10 @@ static int schedule(const std::vector<TextDesc> &ds, Sched &s)
             const bool has = deep && (d.K + st + 1 < d.L);
             push(s.b_walk[st], aw[st], has ? (1ull << (d.K + st)) : 0);
         }
-        for (uint32_t g = 0; g < d.G; g++)
+        for (uint32_t g = 0; g < d.G; g++) {
             if (group_bits(d, g) > 0) s.any_levels[g] = true;
+            s.rmask[g] |= (g + 1 < d.G) ? 2u : 1u;
+        }
         s.bmask |= (d.b == 1) ? 1u : (d.b == 2 ? 2u : 4u);
         s.max_levels = std::max(s.max_levels, d.L);
         if (deep) s.max_tmp_levels = std::max(s.max_tmp_levels, d.L - d.K);
@@ -266,6 +270,7 @@ static hipError_t run_build(const TextDesc *d_descs, const Sched &s, const DevBa
         gl.nchunks = s.nchunks;
         gl.any_levels = s.any_levels[g];
         gl.bmask = s.bmask;
+        gl.rmask = s.rmask[g];
         gl.grid_cap = grid_cap;
         if ((e = launch_group(d_descs, gl, ctx)) != hipSuccess) return e;
     }

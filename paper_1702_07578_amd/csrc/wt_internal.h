@@ -126,6 +126,7 @@ struct GroupLaunch {
     uint32_t nchunks;  // total chunk items
     bool any_levels;   // some text has at least one level in this group
     uint32_t bmask;    // symbol widths present: bit 0 (1 byte), 1 (2 bytes), 2 (4 bytes)
+    uint32_t rmask;    // bit 0: some text ends with group g; bit 1: some text goes on
     uint32_t grid_cap; // 0: one workgroup per item
 };
 

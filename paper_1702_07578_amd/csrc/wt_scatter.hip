@@ -26,27 +26,43 @@ namespace wtg {
 
 constexpr uint32_t kChunks = kWaveTile / 64;              // chunks of 64 symbols per tile
 constexpr uint32_t kRuns = (1u << kMaxGroupBits) - 1;      // (level, key) pairs of levels 0..K-1
-constexpr uint32_t kKeyTab = (2u << kMaxGroupBits) - 1;    // (level, key) pairs of levels 0..K
-// full output words of one tile over all levels (<= kChunks per level), and
-// the finest key prefix sums (2^K + 1 entries) that share their array
-constexpr uint32_t kMaxWords = (kMaxGroupBits * kChunks > (1u << kMaxGroupBits) + 1)
-                                   ? kMaxGroupBits * kChunks : (1u << kMaxGroupBits) + 1;
-constexpr uint32_t kNoPend = 0xFFFFFFFFu;
-constexpr uint32_t kForeignLow = 0x80000000u;  // pending word's low bits belong to another range
+constexpr uint32_t kKeys = 1u << kMaxGroupBits;            // keys of level K (the finest)
+// full output words of one tile over all levels (<= kChunks per level)
+constexpr uint32_t kMaxWords = kMaxGroupBits * kChunks;
+// state of the word a key's run ends in (that word is G >> 6 of the key's
+// next run): none, kept in LDS, or kept with low bits that belong to
+// another range (that word is then completed by atomic OR)
+constexpr uint8_t kNoPend = 0, kPend = 1, kPendForeign = 2;
 
-// One wave's LDS.  Tables are indexed lvl_off(a) + key for level a.
-template <typename E>
+// One wave's LDS.  Tables of levels 0..Kg-1 are indexed lvl_off(a) + key.
+// REORDER (the group's symbols move on to the next group's sequence) adds
+// the tables of level Kg, the finest key.
+template <typename E, bool REORDER>
 struct WaveSmem {
-    uint64_t bits[kMaxGroupBits][kChunks];  // level a of the tile, in order a
-    uint64_t pend_v[kRuns];                 // bits so far of the word a key's run ends in
-    uint32_t h[kKeyTab];                    // the tile's count of every key
-    uint32_t G[kKeyTab];                    // global start of the key's bits for this tile
-    uint32_t pend_w[kRuns];                 // that word's index (kNoPend: none)
-    uint16_t lo[kKeyTab];                   // start of the key in the tile order of its level
-    uint16_t wb[kRuns];                     // first full word of every run, all levels
-    uint16_t kw[kMaxWords];                 // run of every full word (also a scratch scan)
-    E elem[kWaveTile];                      // the tile, in its next order
+    // level a of the tile in order a; while the tables are built (and at a
+    // range start) it holds the finest key counts and their prefix sums
+    uint64_t bits[kMaxGroupBits][kChunks];
+    uint64_t pend_v[kRuns];  // bits so far of the word a key's run ends in
+    uint32_t G[kRuns];       // global start of the key's bits for this tile
+    uint16_t h[kRuns];       // the tile's count of every key
+    uint16_t lo[kRuns];      // start of the key in the tile order of its level
+    uint8_t pend[kRuns];     // state of that word
+    uint32_t GK[REORDER ? kKeys : 1];
+    uint16_t hK[REORDER ? kKeys : 1];
+    uint16_t loK[REORDER ? kKeys : 1];
+    union {
+        E elem[kWaveTile];  // the tile, in its next order (loading and splits)
+        struct {            // copy-out, after the splits
+            uint16_t kw[kMaxWords];  // run of every full word
+            uint16_t wb[kRuns];      // first full word of every run, all levels
+        } co;
+    };
+
+    __device__ uint32_t *tmp32() { return (uint32_t *)&bits[0][0]; }              // kKeys entries
+    __device__ uint16_t *tmp16() { return (uint16_t *)(tmp32() + kKeys); }        // kKeys + 1 entries
 };
+static_assert(sizeof(uint64_t) * kMaxGroupBits * kChunks >= 4 * kKeys + 2 * (kKeys + 1),
+              "level buffer too small for the table scratch");
 
 // orders the wave's LDS accesses (the wave runs in lockstep; no s_barrier)
 __device__ inline void wave_sync()
@@ -119,27 +135,34 @@ __device__ inline void put_lane(uint32_t &acc_lo, uint32_t &acc_hi, uint64_t B)
 
 // G at the first tile of range r: the range prefix of every finest key merged
 // upward, plus the key bases of each level.
+template <typename E, bool REORDER>
 __device__ inline void wave_range_start(const TextDesc &d, uint32_t g, uint32_t Kg, uint32_t r,
-                                        uint32_t *G)
+                                        WaveSmem<E, REORDER> &sm)
 {
     const uint32_t lane = lane_id();
     const uint32_t nk = 1u << Kg;
     const uint32_t *TP = d.TP + (uint64_t)r * nk;
-    for (uint32_t k = lane; k < nk; k += 64) G[lvl_off(Kg) + k] = TP[k];
+    uint32_t *T = sm.tmp32();
+    for (uint32_t k = lane; k < nk; k += 64) T[k] = TP[k];
     wave_sync();
     for (uint32_t a = Kg; a-- > 0;) {
+        const uint32_t *up = (a + 1 == Kg) ? T : sm.G + lvl_off(a + 1);
         for (uint32_t k = lane; k < (1u << a); k += 64)
-            G[lvl_off(a) + k] = G[lvl_off(a + 1) + 2 * k] + G[lvl_off(a + 1) + 2 * k + 1];
+            sm.G[lvl_off(a) + k] = up[2 * k] + up[2 * k + 1];
         wave_sync();
     }
-    for (uint32_t a = 0; a <= Kg; a++) {
+    for (uint32_t a = 0; a < Kg; a++) {
         const uint32_t *kb = (use_prefix_order(d, g, a, Kg) ? d.KBid : d.KBpi) + lvl_off(a);
-        for (uint32_t k = lane; k < (1u << a); k += 64) G[lvl_off(a) + k] += kb[k];
+        for (uint32_t k = lane; k < (1u << a); k += 64) sm.G[lvl_off(a) + k] += kb[k];
+    }
+    if (REORDER) {
+        const uint32_t *kb = d.KBpi + lvl_off(Kg);
+        for (uint32_t k = lane; k < nk; k += 64) sm.GK[k] = T[k] + kb[k];
     }
     wave_sync();
 }
 
-// full words of run e: [ceil(G/64), floor((G+h)/64))
+// full words of a run: [ceil(G/64), floor((G+h)/64))
 __device__ inline uint32_t full_words(uint32_t gs, uint32_t hh)
 {
     const uint32_t f = (gs + 63) >> 6, l = (uint32_t)(((uint64_t)gs + hh) >> 6);
@@ -149,26 +172,28 @@ __device__ inline uint32_t full_words(uint32_t gs, uint32_t hh)
 // Words that a run of this tile covers completely, all levels at once, by
 // plain stores: the full words of all runs are numbered run by run, and the
 // lanes take consecutive words.
-template <typename E>
-__device__ __attribute__((always_inline)) inline void copy_full_words(const TextDesc &d, uint32_t g, uint32_t Kg, WaveSmem<E> &sm)
+template <typename E, bool REORDER>
+__device__ __attribute__((always_inline)) inline void copy_full_words(const TextDesc &d, uint32_t g,
+                                                                      uint32_t Kg,
+                                                                      WaveSmem<E, REORDER> &sm)
 {
     const uint32_t lane = lane_id();
     const uint32_t nr = lvl_off(Kg);
     const uint32_t total = wave_exscan_n<4>(
         nr, [&](uint32_t e) { return full_words(sm.G[e], sm.h[e]); },
-        [&](uint32_t e, uint32_t x) { sm.wb[e] = (uint16_t)x; });
+        [&](uint32_t e, uint32_t x) { sm.co.wb[e] = (uint16_t)x; });
     // run of every word: the run whose first word it is, carried forward
-    for (uint32_t q = lane; q < total; q += 64) sm.kw[q] = 0;
+    for (uint32_t q = lane; q < total; q += 64) sm.co.kw[q] = 0;
     wave_sync();
     for (uint32_t e = lane; e < nr; e += 64)
-        if (full_words(sm.G[e], sm.h[e]) != 0) sm.kw[sm.wb[e]] = (uint16_t)e;
+        if (full_words(sm.G[e], sm.h[e]) != 0) sm.co.kw[sm.co.wb[e]] = (uint16_t)e;
     wave_sync();
-    constexpr uint32_t PER = (kMaxGroupBits * kChunks + 63) / 64;
+    constexpr uint32_t PER = (kMaxWords + 63) / 64;
     uint32_t m = 0;
 #pragma unroll
     for (uint32_t i = 0; i < PER; i++) {
         const uint32_t q = lane * PER + i;
-        if (q < total) m = max(m, (uint32_t)sm.kw[q]);
+        if (q < total) m = max(m, (uint32_t)sm.co.kw[q]);
     }
     // carry: the maximum over the lanes below
     uint32_t run = wave_incl_max(m);
@@ -177,15 +202,15 @@ __device__ __attribute__((always_inline)) inline void copy_full_words(const Text
     for (uint32_t i = 0; i < PER; i++) {
         const uint32_t q = lane * PER + i;
         if (q < total) {
-            run = max(run, (uint32_t)sm.kw[q]);
-            sm.kw[q] = (uint16_t)run;
+            run = max(run, (uint32_t)sm.co.kw[q]);
+            sm.co.kw[q] = (uint16_t)run;
         }
     }
     wave_sync();
     for (uint32_t q = lane; q < total; q += 64) {
-        const uint32_t e = sm.kw[q], a = level_of(e);
+        const uint32_t e = sm.co.kw[q], a = level_of(e);
         const uint32_t gs = sm.G[e];
-        const uint64_t gw = ((gs + 63) >> 6) + (q - sm.wb[e]);
+        const uint64_t gw = ((gs + 63) >> 6) + (q - sm.co.wb[e]);
         if (gw < d.W)
             level_ptr(d, g, a)[gw] =
                 stream_bits(sm.bits[a], sm.lo[e] + (uint32_t)((gw << 6) - gs), 64);
@@ -196,76 +221,78 @@ __device__ __attribute__((always_inline)) inline void copy_full_words(const Text
 // First and last word of every run (one lane per run, all levels): merged
 // with the word kept from earlier tiles of the range, stored when complete,
 // kept otherwise.
-template <typename E>
-__device__ __attribute__((always_inline)) inline void run_end_words(const TextDesc &d, uint32_t g, uint32_t Kg, WaveSmem<E> &sm)
+template <typename E, bool REORDER>
+__device__ __attribute__((always_inline)) inline void run_end_words(const TextDesc &d, uint32_t g,
+                                                                    uint32_t Kg,
+                                                                    WaveSmem<E, REORDER> &sm)
 {
     for (uint32_t e = lane_id(); e < lvl_off(Kg); e += 64) {
         const uint32_t hh = sm.h[e];
         if (hh == 0) continue;
-        const uint32_t a = 31 - __clz(e + 1);
+        const uint32_t a = level_of(e);
         uint64_t *out = level_ptr(d, g, a);
         const uint64_t *src = sm.bits[a];
         const uint32_t ls = sm.lo[e];
         const uint64_t gs = sm.G[e], ge = gs + hh;
         const uint64_t fw = gs >> 6, lw = (ge - 1) >> 6;
-        uint32_t newp = kNoPend;
+        uint8_t newp = kNoPend;
         uint64_t newv = 0;
         if ((gs & 63) != 0 || hh < 64) {
             const uint64_t b1 = ge < ((fw + 1) << 6) ? ge : ((fw + 1) << 6);
             uint64_t val = stream_bits(src, ls, (uint32_t)(b1 - gs)) << (gs & 63);
             bool lowok = (gs & 63) == 0;
-            const uint32_t pw = sm.pend_w[e];
-            if (!lowok && pw != kNoPend && (pw & ~kForeignLow) == fw) {
+            const uint8_t pw = sm.pend[e];
+            if (!lowok && pw != kNoPend) {  // the kept word is fw
                 val |= sm.pend_v[e];
-                lowok = (pw & kForeignLow) == 0;
+                lowok = pw == kPend;
             }
             if (b1 == ((fw + 1) << 6)) {
                 if (fw >= d.W) continue;  // never for consistent tables
                 if (lowok) out[fw] = val;
                 else atomicOr((unsigned long long *)&out[fw], (unsigned long long)val);
             } else {
-                newp = (uint32_t)fw | (lowok ? 0u : kForeignLow);
+                newp = lowok ? kPend : kPendForeign;
                 newv = val;
             }
         }
         if (lw != fw && (ge & 63) != 0 && lw < d.W) {
-            newp = (uint32_t)lw;
+            newp = kPend;
             newv = stream_bits(src, ls + (uint32_t)((lw << 6) - gs), (uint32_t)(ge - (lw << 6)));
         }
-        sm.pend_w[e] = newp;
+        sm.pend[e] = newp;
         sm.pend_v[e] = newv;
     }
 }
 
-// One split (or, MODE 2, only the ballots) of the tile by bit `bit`: the
-// ballots are level a in the current order; MODE 0 writes every symbol to
-// its place in the next order in LDS, MODE 1 to its place in the next
-// group's sequence (global).  A tile shorter than kWaveTile is padded with
+// One split (or, with SPLIT false, only the ballots) of the tile by bit
+// `bit`: the ballots are level a in the current order, and every symbol is
+// written to its place in the next order in LDS.  base1 is the tile's
+// number of zeros of that bit.  A tile shorter than kWaveTile is padded with
 // symbols whose bits are all one: they sort after every real symbol at every
 // level, so the real symbols keep their places and the padding fills the
 // end of every level's stream.
-template <typename E, int MODE>
-__device__ __attribute__((always_inline)) inline void split_pass(
-    const TextDesc &d, uint32_t (&v)[kChunks], bool padded, uint32_t a, uint32_t bit,
-    uint32_t shift, uint32_t Kg, E *gout, WaveSmem<E> &sm)
+template <typename E, bool REORDER, bool SPLIT>
+__device__ __attribute__((always_inline)) inline void split_pass(uint32_t (&v)[kChunks], uint32_t a,
+                                                                 uint32_t bit, uint32_t base1,
+                                                                 WaveSmem<E, REORDER> &sm)
 {
     const uint32_t lane = lane_id();
-    const uint32_t kmask = (1u << Kg) - 1u;
-    const uint32_t neg_lane = 0u - lane;
+    uint32_t neg_lane = 0u - lane;
     // LDS address of the element buffer
     const uint32_t ebase = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) E *)sm.elem;
     uint32_t acc_lo = 0, acc_hi = 0;
-    // the zeros of level a in the tile: the start of the first key whose bit
-    // a is one, in the order of level a + 1
     uint32_t base0 = 0;
-    uint32_t base1 = MODE == 2 ? 0u : __builtin_amdgcn_readfirstlane((uint32_t)sm.lo[lvl_off(a + 1) + 1]);
+    base1 = __builtin_amdgcn_readfirstlane(base1);
     static_for<0, kChunks>([&](auto ci) {
         constexpr uint32_t c = decltype(ci)::value;
+        // keeps each chunk's ranks from being computed ahead of time (which
+        // would hold one register per chunk)
+        asm volatile("" : "+v"(neg_lane));
         const uint32_t x = v[c];
         const bool one = (x & bit) != 0;
         const uint64_t B = __ballot(one);
         put_lane<c>(acc_lo, acc_hi, B);
-        if (MODE == 0) {
+        if (SPLIT) {
             // m = (ones before this lane in the chunk) - lane; a one goes to
             // base1 + m + lane, a zero to base0 - m.  The bases are kept
             // opaque so that they stay scalar.
@@ -276,18 +303,6 @@ __device__ __attribute__((always_inline)) inline void split_pass(
             const uint32_t i1 = s1 + (m + lane) * (uint32_t)sizeof(E);
             const uint32_t i0 = s0 - m * (uint32_t)sizeof(E);
             *(__attribute__((address_space(3))) E *)(uintptr_t)(one ? i1 : i0) = (E)x;
-        } else if (MODE == 1) {
-            const uint32_t r1 = mbcnt64(B);
-            const uint32_t dst = one ? base1 + r1 : base0 + (lane - r1);
-            const uint32_t e = lvl_off(Kg) + ((x >> shift) & kmask);
-            const uint32_t rank = dst - sm.lo[e];
-            // padding ranks past the key's count
-            if (!padded || rank < sm.h[e]) {
-                const uint32_t gi = sm.G[e] + rank;
-                if (gi < d.n) gout[gi] = (E)x;
-            }
-        }
-        if (MODE != 2) {
             const uint32_t ones = __popcll(B);
             base0 += 64u - ones;
             base1 += ones;
@@ -299,10 +314,10 @@ __device__ __attribute__((always_inline)) inline void split_pass(
 
 // One tile of kWaveTile symbols (the text's last tile may be shorter; it is
 // padded).
-template <typename E>
+template <typename E, bool REORDER>
 __device__ __attribute__((always_inline)) inline void wave_tile(const TextDesc &d, uint32_t g,
                                                                 uint32_t Kg, uint32_t t,
-                                                                WaveSmem<E> &sm)
+                                                                WaveSmem<E, REORDER> &sm)
 {
     const uint32_t lane = lane_id();
     const uint64_t start = (uint64_t)t * kWaveTile;
@@ -310,14 +325,14 @@ __device__ __attribute__((always_inline)) inline void wave_tile(const TextDesc &
     const bool padded = len < kWaveTile;
     const uint32_t shift = d.L - g * d.K - Kg;
     const uint32_t nk = 1u << Kg, kmask = nk - 1u;
-    const bool reorder = (g + 1 < d.G);
     const E *src = (const E *)seq_in(d, g) + start + lane;
-    uint32_t *h = sm.h;
+    uint32_t *cnt = sm.tmp32();
+    uint16_t *P = sm.tmp16();
 
     // 1. the tile, in text order, through registers into LDS, counting the
     //    finest keys by LDS atomics on the way (the registers are free while
     //    the tables are built)
-    for (uint32_t k = lane; k < nk; k += 64) h[lvl_off(Kg) + k] = 0;
+    for (uint32_t k = lane; k < nk; k += 64) cnt[k] = 0;
     wave_sync();
     {
         uint32_t v[kChunks];
@@ -325,65 +340,78 @@ __device__ __attribute__((always_inline)) inline void wave_tile(const TextDesc &
 #pragma unroll
             for (uint32_t c = 0; c < kChunks; c++) v[c] = src[c * 64];
 #pragma unroll
-            for (uint32_t c = 0; c < kChunks; c++)
-                atomicAdd(&h[lvl_off(Kg) + ((v[c] >> shift) & kmask)], 1u);
+            for (uint32_t c = 0; c < kChunks; c++) atomicAdd(&cnt[(v[c] >> shift) & kmask], 1u);
         } else {
 #pragma unroll
             for (uint32_t c = 0; c < kChunks; c++)
                 v[c] = (c * 64 + lane < len) ? (uint32_t)src[c * 64] : (uint32_t)(E)~0u;
 #pragma unroll
             for (uint32_t c = 0; c < kChunks; c++)
-                if (c * 64 + lane < len) atomicAdd(&h[lvl_off(Kg) + ((v[c] >> shift) & kmask)], 1u);
+                if (c * 64 + lane < len) atomicAdd(&cnt[(v[c] >> shift) & kmask], 1u);
         }
 #pragma unroll
         for (uint32_t c = 0; c < kChunks; c++) sm.elem[c * 64 + lane] = (E)v[c];
     }
     wave_sync();
 
-    // 2. the tile's count of every key: the others as differences of the
-    //    finest prefix sums P (padding not counted)
-    uint16_t *P = sm.kw;
+    // 2. the tile's count of every key of levels 0..Kg-1, as differences of
+    //    the prefix sums P of the finest counts (padding not counted)
     wave_exscan_n<4>(
-        nk, [&](uint32_t k) { return h[lvl_off(Kg) + k]; },
-        [&](uint32_t k, uint32_t x) { P[k] = (uint16_t)x; });
+        nk, [&](uint32_t k) { return cnt[k]; }, [&](uint32_t k, uint32_t x) { P[k] = (uint16_t)x; });
     if (lane == 0) P[nk] = (uint16_t)len;
+    if (REORDER)
+        for (uint32_t k = lane; k < nk; k += 64) sm.hK[k] = (uint16_t)cnt[k];
     wave_sync();
     for (uint32_t e = lane; e < lvl_off(Kg); e += 64) {
         const uint32_t a = level_of(e), k = e - lvl_off(a), sh = Kg - a;
-        h[e] = (uint32_t)P[(k + 1) << sh] - (uint32_t)P[k << sh];
+        sm.h[e] = (uint16_t)(P[(k + 1) << sh] - P[k << sh]);
     }
     wave_sync();
     // 3. start of every key in the tile order of its level (keys in reversed
-    //    order): one scan over the levels one after the other, each of which
-    //    adds len; level Kg only when the symbols move on to the next group
-    const uint32_t lmax = reorder ? Kg : Kg - 1;
-    wave_exscan_n<8>(
-        lvl_off(lmax + 1),
-        [&](uint32_t i) {
-            const uint32_t a = level_of(i);
-            return h[lvl_off(a) + rev_bits(i - lvl_off(a), a)];
-        },
-        [&](uint32_t i, uint32_t x) {
-            const uint32_t a = level_of(i);
-            sm.lo[lvl_off(a) + rev_bits(i - lvl_off(a), a)] = (uint16_t)(x - a * len);
-        });
+    //    order)
+    if (lane == 0) sm.lo[0] = 0;
+    for (uint32_t a = 1; a < Kg; a++) {
+        const uint32_t o = lvl_off(a);
+        wave_exscan_n<4>(
+            1u << a, [&](uint32_t i) { return (uint32_t)sm.h[o + rev_bits(i, a)]; },
+            [&](uint32_t i, uint32_t x) { sm.lo[o + rev_bits(i, a)] = (uint16_t)x; });
+    }
+    if (REORDER)
+        wave_exscan_n<4>(
+            nk, [&](uint32_t i) { return (uint32_t)sm.hK[rev_bits(i, Kg)]; },
+            [&](uint32_t i, uint32_t x) { sm.loK[rev_bits(i, Kg)] = (uint16_t)x; });
     wave_sync();
 
-    // 4. split by one bit at a time; the ballots are the levels
+    // 4. split by one bit at a time; the ballots are the levels.  The zeros
+    //    of bit a in the tile: the start of the first key whose bit a is one,
+    //    in the order of level a + 1.
     uint32_t v[kChunks];
 #pragma unroll
     for (uint32_t c = 0; c < kChunks; c++) v[c] = sm.elem[c * 64 + lane];
     wave_sync();
-    E *gout = (E *)seq_out(d, g);
     for (uint32_t a = 0; a + 1 < Kg; a++) {
-        split_pass<E, 0>(d, v, padded, a, 1u << (shift + Kg - 1 - a), shift, Kg, gout, sm);
+        split_pass<E, REORDER, true>(v, a, 1u << (shift + Kg - 1 - a), sm.lo[lvl_off(a + 1) + 1], sm);
         wave_sync();
 #pragma unroll
         for (uint32_t c = 0; c < kChunks; c++) v[c] = sm.elem[c * 64 + lane];
         wave_sync();
     }
-    if (reorder) split_pass<E, 1>(d, v, padded, Kg - 1, 1u << shift, shift, Kg, gout, sm);
-    else split_pass<E, 2>(d, v, padded, Kg - 1, 1u << shift, shift, Kg, gout, sm);
+    if (REORDER) {
+        // the last split orders the tile by its reversed Kg-bit key: each
+        // key's symbols, in text order, go to the key's place in the next
+        // group's sequence (padding sorts last and is dropped)
+        split_pass<E, REORDER, true>(v, Kg - 1, 1u << shift, sm.loK[1], sm);
+        wave_sync();
+        E *gout = (E *)seq_out(d, g);
+        for (uint32_t p = lane; p < len; p += 64) {
+            const E x = sm.elem[p];
+            const uint32_t k = (x >> shift) & kmask;
+            const uint32_t gi = sm.GK[k] + (p - sm.loK[k]);
+            if (gi < d.n) gout[gi] = x;
+        }
+    } else {
+        split_pass<E, REORDER, false>(v, Kg - 1, 1u << shift, 0u, sm);
+    }
     wave_sync();
 
     // 5. every level's runs to their interval starts
@@ -391,66 +419,75 @@ __device__ __attribute__((always_inline)) inline void wave_tile(const TextDesc &
     run_end_words(d, g, Kg, sm);
     wave_sync();
     // the next tile's runs start where this tile's end
-    for (uint32_t e = lane; e < lvl_off(Kg + 1); e += 64) sm.G[e] += h[e];
+    for (uint32_t e = lane; e < lvl_off(Kg); e += 64) sm.G[e] += sm.h[e];
+    if (REORDER)
+        for (uint32_t k = lane; k < nk; k += 64) sm.GK[k] += sm.hK[k];
     wave_sync();
 }
 
-template <typename E>
-__device__ void wave_range(const TextDesc &d, uint32_t g, uint32_t Kg, uint32_t r, WaveSmem<E> &sm)
+template <typename E, bool REORDER>
+__device__ void wave_range(const TextDesc &d, uint32_t g, uint32_t Kg, uint32_t r,
+                           WaveSmem<E, REORDER> &sm)
 {
     const uint32_t lane = lane_id();
-    wave_range_start(d, g, Kg, r, sm.G);
-    for (uint32_t e = lane; e < kRuns; e += 64) sm.pend_w[e] = kNoPend;
+    wave_range_start(d, g, Kg, r, sm);
+    for (uint32_t e = lane; e < kRuns; e += 64) sm.pend[e] = kNoPend;
     wave_sync();
     const uint32_t t0 = r * d.R, t1 = min(d.ntiles, t0 + d.R);
-    for (uint32_t t = t0; t < t1; t++) wave_tile<E>(d, g, Kg, t, sm);
+    for (uint32_t t = t0; t < t1; t++) wave_tile(d, g, Kg, t, sm);
     // words still open at the end of the range are shared with the next one
     for (uint32_t e = lane; e < lvl_off(Kg); e += 64) {
-        const uint32_t pw = sm.pend_w[e];
-        if (pw == kNoPend) continue;
-        const uint32_t a = 31 - __clz(e + 1);
-        if ((pw & ~kForeignLow) < d.W)
-            atomicOr((unsigned long long *)&level_ptr(d, g, a)[pw & ~kForeignLow],
+        if (sm.pend[e] == kNoPend) continue;
+        const uint64_t wd = sm.G[e] >> 6;
+        if (wd < d.W)
+            atomicOr((unsigned long long *)&level_ptr(d, g, level_of(e))[wd],
                      (unsigned long long)sm.pend_v[e]);
     }
     wave_sync();
 }
 
 // Work item = (text, range); wave w of workgroup b takes items
-// b * kScatWaves + w, then strides by the whole grid.
-template <typename E>
+// b * kScatWaves + w, then strides by the whole grid.  The REORDER variant
+// takes the texts whose symbols move on to another group after group g.
+template <typename E, bool REORDER>
 __global__ __launch_bounds__(kScatWaves * 64) void k_scatter(const TextDesc *__restrict__ descs,
                                                              const uint32_t *__restrict__ bases,
                                                              uint32_t nd, uint32_t nitems, uint32_t g)
 {
-    __shared__ WaveSmem<E> sm[kScatWaves];
+    __shared__ WaveSmem<E, REORDER> sm[kScatWaves];
     const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (uint32_t item = blockIdx.x * kScatWaves + w; item < nitems;
          item += gridDim.x * kScatWaves) {
         const uint32_t ti = find_text(bases, nd, item);
         const TextDesc &d = descs[ti];
         const uint32_t r = item - item_base(bases, nd, ti);
-        if (d.b != sizeof(E) || g >= d.G || r >= d.nranges) continue;
+        if (d.b != sizeof(E) || g >= d.G || r >= d.nranges || (g + 1 < d.G) != REORDER) continue;
         const uint32_t Kg = group_bits(d, g);
         if (Kg == 0) continue;
-        wave_range<E>(d, g, Kg, r, sm[w]);
+        wave_range<E, REORDER>(d, g, Kg, r, sm[w]);
     }
+}
+
+template <typename E>
+static void launch_width(const TextDesc *d_descs, const GroupLaunch &gl, uint32_t grid,
+                         const LaunchCtx &ctx)
+{
+    const dim3 block(kScatWaves * 64);
+    if (gl.rmask & 1u)
+        hipLaunchKernelGGL((k_scatter<E, false>), dim3(grid), block, 0, ctx.stream, d_descs,
+                           gl.range_bases, gl.nd, gl.nranges, gl.g);
+    if (gl.rmask & 2u)
+        hipLaunchKernelGGL((k_scatter<E, true>), dim3(grid), block, 0, ctx.stream, d_descs,
+                           gl.range_bases, gl.nd, gl.nranges, gl.g);
 }
 
 hipError_t launch_scatter(const TextDesc *d_descs, const GroupLaunch &gl, const LaunchCtx &ctx)
 {
     uint32_t grid = (gl.nranges + kScatWaves - 1) / kScatWaves;
     if (gl.grid_cap && grid > gl.grid_cap) grid = gl.grid_cap;
-    const dim3 block(kScatWaves * 64);
-    if (gl.bmask & 1u)
-        hipLaunchKernelGGL(k_scatter<uint8_t>, dim3(grid), block, 0, ctx.stream, d_descs,
-                           gl.range_bases, gl.nd, gl.nranges, gl.g);
-    if (gl.bmask & 2u)
-        hipLaunchKernelGGL(k_scatter<uint16_t>, dim3(grid), block, 0, ctx.stream, d_descs,
-                           gl.range_bases, gl.nd, gl.nranges, gl.g);
-    if (gl.bmask & 4u)
-        hipLaunchKernelGGL(k_scatter<uint32_t>, dim3(grid), block, 0, ctx.stream, d_descs,
-                           gl.range_bases, gl.nd, gl.nranges, gl.g);
+    if (gl.bmask & 1u) launch_width<uint8_t>(d_descs, gl, grid, ctx);
+    if (gl.bmask & 2u) launch_width<uint16_t>(d_descs, gl, grid, ctx);
+    if (gl.bmask & 4u) launch_width<uint32_t>(d_descs, gl, grid, ctx);
     if (ctx.after) ctx.after(ctx.user, KID_SCATTER);
     return hipGetLastError();
 }
