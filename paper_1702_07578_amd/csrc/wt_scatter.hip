@@ -47,6 +47,7 @@ struct WaveSmem {
     uint16_t h[kRuns];       // the tile's count of every key
     uint16_t lo[kRuns];      // start of the key in the tile order of its level
     uint8_t pend[kRuns];     // state of that word
+    uint32_t lvw[kMaxGroupBits];  // word offset of level a from the group's base pointer
     uint32_t GK[REORDER ? kKeys : 1];
     uint16_t hK[REORDER ? kKeys : 1];
     uint16_t loK[REORDER ? kKeys : 1];
@@ -133,6 +134,18 @@ __device__ inline void put_lane(uint32_t &acc_lo, uint32_t &acc_hi, uint64_t B)
         : "m0");
 }
 
+// Base of the bit vectors group g writes: the output levels, or, for the
+// WT's later groups, its temporary WM levels; level a of the group starts
+// sm.lvw[a] words after it.  Word offsets fit 32 bits (L W < 2^31).
+__device__ inline uint64_t *group_base(const TextDesc &d, uint32_t g)
+{
+    return (d.kind == WT_TREE && g > 0) ? d.tmp_bits : d.bits;
+}
+__device__ inline uint32_t group_level0(const TextDesc &d, uint32_t g)
+{
+    return (d.kind == WT_TREE && g > 0) ? (g - 1) * d.K : g * d.K;
+}
+
 // G at the first tile of range r: the range prefix of every finest key merged
 // upward, plus the key bases of each level.
 template <typename E, bool REORDER>
@@ -159,6 +172,7 @@ __device__ inline void wave_range_start(const TextDesc &d, uint32_t g, uint32_t 
         const uint32_t *kb = d.KBpi + lvl_off(Kg);
         for (uint32_t k = lane; k < nk; k += 64) sm.GK[k] = T[k] + kb[k];
     }
+    if (lane < Kg) sm.lvw[lane] = (group_level0(d, g) + lane) * (uint32_t)d.W;
     wave_sync();
 }
 
@@ -207,13 +221,13 @@ __device__ __attribute__((always_inline)) inline void copy_full_words(const Text
         }
     }
     wave_sync();
+    uint64_t *base = group_base(d, g);
+    const uint32_t W = (uint32_t)d.W;
     for (uint32_t q = lane; q < total; q += 64) {
         const uint32_t e = sm.co.kw[q], a = level_of(e);
         const uint32_t gs = sm.G[e];
-        const uint64_t gw = ((gs + 63) >> 6) + (q - sm.co.wb[e]);
-        if (gw < d.W)
-            level_ptr(d, g, a)[gw] =
-                stream_bits(sm.bits[a], sm.lo[e] + (uint32_t)((gw << 6) - gs), 64);
+        const uint32_t gw = ((gs + 63) >> 6) + (q - sm.co.wb[e]);
+        if (gw < W) base[sm.lvw[a] + gw] = stream_bits(sm.bits[a], sm.lo[e] + ((gw << 6) - gs), 64);
     }
     wave_sync();
 }
@@ -226,28 +240,32 @@ __device__ __attribute__((always_inline)) inline void run_end_words(const TextDe
                                                                     uint32_t Kg,
                                                                     WaveSmem<E, REORDER> &sm)
 {
+    uint64_t *base = group_base(d, g);
+    const uint32_t W = (uint32_t)d.W;
     for (uint32_t e = lane_id(); e < lvl_off(Kg); e += 64) {
         const uint32_t hh = sm.h[e];
         if (hh == 0) continue;
         const uint32_t a = level_of(e);
-        uint64_t *out = level_ptr(d, g, a);
+        uint64_t *out = base + sm.lvw[a];
         const uint64_t *src = sm.bits[a];
         const uint32_t ls = sm.lo[e];
-        const uint64_t gs = sm.G[e], ge = gs + hh;
-        const uint64_t fw = gs >> 6, lw = (ge - 1) >> 6;
+        // positions are below n < 2^32; ge may equal n
+        const uint32_t gs = sm.G[e], ge = gs + hh;
+        const uint32_t fw = gs >> 6, lw = (ge - 1) >> 6;
+        const uint32_t off = gs & 63;
         uint8_t newp = kNoPend;
         uint64_t newv = 0;
-        if ((gs & 63) != 0 || hh < 64) {
-            const uint64_t b1 = ge < ((fw + 1) << 6) ? ge : ((fw + 1) << 6);
-            uint64_t val = stream_bits(src, ls, (uint32_t)(b1 - gs)) << (gs & 63);
-            bool lowok = (gs & 63) == 0;
+        if (off != 0 || hh < 64) {
+            const uint32_t cnt = min(hh, 64u - off);  // bits of the run in word fw
+            uint64_t val = stream_bits(src, ls, cnt) << off;
+            bool lowok = off == 0;
             const uint8_t pw = sm.pend[e];
             if (!lowok && pw != kNoPend) {  // the kept word is fw
                 val |= sm.pend_v[e];
                 lowok = pw == kPend;
             }
-            if (b1 == ((fw + 1) << 6)) {
-                if (fw >= d.W) continue;  // never for consistent tables
+            if (off + cnt == 64) {
+                if (fw >= W) continue;  // never for consistent tables
                 if (lowok) out[fw] = val;
                 else atomicOr((unsigned long long *)&out[fw], (unsigned long long)val);
             } else {
@@ -255,9 +273,9 @@ __device__ __attribute__((always_inline)) inline void run_end_words(const TextDe
                 newv = val;
             }
         }
-        if (lw != fw && (ge & 63) != 0 && lw < d.W) {
+        if (lw != fw && (ge & 63) != 0 && lw < W) {
             newp = kPend;
-            newv = stream_bits(src, ls + (uint32_t)((lw << 6) - gs), (uint32_t)(ge - (lw << 6)));
+            newv = stream_bits(src, ls + ((lw << 6) - gs), ge & 63);
         }
         sm.pend[e] = newp;
         sm.pend_v[e] = newv;
@@ -369,13 +387,19 @@ __device__ __attribute__((always_inline)) inline void wave_tile(const TextDesc &
     wave_sync();
     // 3. start of every key in the tile order of its level (keys in reversed
     //    order)
+    //    One scan runs over levels 1..Kg-1 one after the other: each level's
+    //    counts add up to len, so level a starts at (a - 1) len.
     if (lane == 0) sm.lo[0] = 0;
-    for (uint32_t a = 1; a < Kg; a++) {
-        const uint32_t o = lvl_off(a);
-        wave_exscan_n<4>(
-            1u << a, [&](uint32_t i) { return (uint32_t)sm.h[o + rev_bits(i, a)]; },
-            [&](uint32_t i, uint32_t x) { sm.lo[o + rev_bits(i, a)] = (uint16_t)x; });
-    }
+    wave_exscan_n<4>(
+        lvl_off(Kg) - 1,
+        [&](uint32_t i) {
+            const uint32_t a = level_of(i + 1);
+            return (uint32_t)sm.h[lvl_off(a) + rev_bits(i + 1 - lvl_off(a), a)];
+        },
+        [&](uint32_t i, uint32_t x) {
+            const uint32_t a = level_of(i + 1);
+            sm.lo[lvl_off(a) + rev_bits(i + 1 - lvl_off(a), a)] = (uint16_t)(x - (a - 1) * len);
+        });
     if (REORDER)
         wave_exscan_n<4>(
             nk, [&](uint32_t i) { return (uint32_t)sm.hK[rev_bits(i, Kg)]; },
@@ -438,9 +462,9 @@ __device__ void wave_range(const TextDesc &d, uint32_t g, uint32_t Kg, uint32_t 
     // words still open at the end of the range are shared with the next one
     for (uint32_t e = lane; e < lvl_off(Kg); e += 64) {
         if (sm.pend[e] == kNoPend) continue;
-        const uint64_t wd = sm.G[e] >> 6;
-        if (wd < d.W)
-            atomicOr((unsigned long long *)&level_ptr(d, g, level_of(e))[wd],
+        const uint32_t wd = sm.G[e] >> 6;
+        if (wd < (uint32_t)d.W)
+            atomicOr((unsigned long long *)&group_base(d, g)[sm.lvw[level_of(e)] + wd],
                      (unsigned long long)sm.pend_v[e]);
     }
     wave_sync();
