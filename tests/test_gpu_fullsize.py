@@ -1,0 +1,78 @@
+"""Parity at the workload sizes, in the launch configuration the benchmark
+uses (default tuning): the texts are too long for a whole oracle build, so
+the oracle supplies sampled level bits (its per-position definition), and
+every other output is checked through properties that hold at any size:
+the zero count of every level, the popcount of every level, the padding
+bits, the directories of every level recomputed by the oracle from the
+GPU's level words, and access at sampled positions."""
+import numpy as np
+import pytest
+
+from tests.gpu_util import lib
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+WT, WM = 0, 1
+SAMPLES = 2048
+
+
+def _zero_counts(T, L):
+    """Zeros of every level: symbols whose bit l is 0 (Section 2, bit(l, a))."""
+    hist = np.bincount(T, minlength=1 << L)
+    sym = np.arange(hist.size, dtype=np.int64)
+    return np.array([int(hist[((sym >> (L - 1 - l)) & 1) == 0].sum()) for l in range(L)],
+                    dtype=np.uint64)
+
+
+def _check_structure(orc, T, L, kind, s, rng):
+    n = T.size
+    assert s.status() == 0
+    bits, zeros, rd, s0, s1 = s.host_arrays()
+    W = bits.shape[1]
+    assert np.array_equal(zeros, _zero_counts(T, L)), "zero counts"
+    pos = np.sort(rng.integers(0, n, size=SAMPLES, dtype=np.uint64))
+    for l in range(L):
+        lv = bits[l]
+        # popcount of the level = symbols whose bit l is 1
+        assert int(np.bitwise_count(lv).sum()) == n - int(zeros[l]), f"level {l} popcount"
+        # bits past n are zero
+        if n % 64:
+            assert int(lv[n // 64]) >> (n % 64) == 0, f"level {l} tail bits"
+        assert not lv[(n + 63) // 64:].any(), f"level {l} padding words"
+        # directories: the oracle's, recomputed from this level's words
+        ord_, os0, os1 = orc.directory(lv, n)
+        cap = orc.sel_capacity(n)
+        assert np.array_equal(rd[l][: W // 8 + 1], ord_), f"rank_dir level {l}"
+        assert np.array_equal(s0[l][:cap], os0), f"sel0 level {l}"
+        assert np.array_equal(s1[l][:cap], os1), f"sel1 level {l}"
+    # level bits at sampled positions: the oracle's per-position definition
+    for l in sorted({0, L // 2, L - 1}):
+        want = orc.sample_level(kind, T, L, l, pos)
+        got = ((bits[l][(pos >> 6).astype(np.int64)] >> (pos & 63)) & 1).astype(np.uint8)
+        bad = np.flatnonzero(got != want)
+        assert bad.size == 0, f"kind {kind} level {l}: {bad.size} of {SAMPLES} sampled bits differ"
+
+
+def _check_access(T, s, rng):
+    import torch
+    p = rng.integers(0, T.size, size=SAMPLES, dtype=np.uint64)
+    got = s.access(torch.from_numpy(p.view(np.int64)).cuda()).cpu().numpy().view(np.uint32)
+    assert np.array_equal(got, T[p.astype(np.int64)].astype(np.uint32)), "access"
+
+
+@pytest.mark.parametrize("workload", ["uniform256", "markov96", "markov4", "zipf20", "uniform16"])
+def test_workload_full_size(orc, workload):
+    import torch
+    from paper_1702_07578_amd import inputs
+    B = lib()
+    T, L = inputs.make(workload)
+    print(f"[full-size] {workload}: n={T.size} b={T.dtype.itemsize} L={L}", flush=True)
+    d = B.to_device(T)
+    rng = np.random.default_rng(7)
+    for kind in (WT, WM):
+        s = B.build(d, T.size, T.dtype.itemsize, L, kind)
+        torch.cuda.synchronize()
+        _check_structure(orc, T, L, kind, s, rng)
+        _check_access(T, s, rng)
+        del s
+        torch.cuda.empty_cache()
