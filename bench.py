@@ -63,6 +63,100 @@ def cpu_baseline(text, L, sample_n):
                       f"(levels and Z) in {dt:.2f} s"}
 
 
+def run_batch(args):
+    """Batched build of the 4096-text workload (WT and WM of every text) in
+    one sequence of launches captured in a HIP graph, with autotuned knobs,
+    against the same builds done one text at a time on the same stream."""
+    import numpy as np
+    import torch
+
+    from paper_1702_07578_amd import autotune
+    from paper_1702_07578_amd import binding as B
+    from paper_1702_07578_amd import inputs
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.time()
+    specs = inputs.batch_specs(args.batch_count, seed=6)
+    texts = [inputs.batch_text(sp) for sp in specs]
+    total = sum(t.size for t, _ in texts)
+    log(f"generated {len(texts)} texts, {total} symbols in {time.time() - t0:.1f}s")
+    d_texts = [B.to_device(t, dev) for t, _ in texts]
+    items, plain = [], []
+    for (t, L), d in zip(texts, d_texts):
+        for kind in (B.WT_TREE, B.WT_MATRIX):
+            items.append((d, t.size, t.dtype.itemsize, L, kind, B.Structure(t.size, L, kind, device=dev)))
+            plain.append(B.Structure(t.size, L, kind, device=dev))
+    torch.cuda.synchronize()
+
+    tune, table = autotune.tune(items, cache_path=args.tune_cache or None, log=log)
+    batch = B.Batch(items, tune=tune)
+    for it in items:
+        it[5].buf.zero_()
+    batch.prepare()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(graph, stream=side):
+            batch.launch(side)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    batch_ms = e0.elapsed_time(e1) / args.steps
+    for it in items:
+        if it[5].status() != 0:
+            raise SystemExit("batched build reported an error status")
+
+    # the same builds, one text at a time on the same stream
+    ws = torch.empty(max(B.workspace_bytes(n, b, L, k) for _, n, b, L, k, _ in items), dtype=torch.uint8,
+                     device=dev)
+    for s in plain:
+        s.buf.zero_()
+
+    def per_text():
+        for (d, n, b, L, kind, _), s in zip(items, plain):
+            B.build(d, n, b, L, kind, ws=ws, out=s)
+
+    per_text()
+    torch.cuda.synchronize()
+    p0, p1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    p0.record()
+    per_text()
+    p1.record()
+    torch.cuda.synchronize()
+    plain_ms = p0.elapsed_time(p1)
+    # every batched structure equals its one-at-a-time build (whole buffers,
+    # both cleared before building)
+    for it, s in zip(items, plain):
+        if not torch.equal(it[5].buf, s.buf):
+            raise SystemExit(f"batched output differs from the plain build (n={it[1]}, L={it[3]})")
+    value = 2 * total / (batch_ms / 1e3)
+    out = {
+        "metric": "batched WT+WM build throughput (symbols/s), one GPU",
+        "value": round(value, 1), "unit": "symbols/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(batch_ms, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u8/u16", "data": "synthetic",
+        "config": {"workload": f"batch: {len(texts)} texts, lengths floor(2^U(10,22)), sigma in "
+                               f"{{4, 256, 2^16}}, uniform or Zipf(1.0); WT and WM of every text in "
+                               f"one graph-captured sequence of launches", "texts": len(texts),
+                   "symbols": total, "tune": {"grid": tune.grid if tune else 0,
+                                               "persist": tune.persist if tune else 0}},
+        "per_text_plain_ms": round(plain_ms, 3),
+        "speedup_vs_per_text": round(plain_ms / batch_ms, 2),
+        "autotune": [{"grid": g, "persist": p, "ms": ms, "status": st} for g, p, ms, st in table],
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,12 +171,17 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain elementwise copy of 1 GiB three times (the reference "
                          "kernel for scaling the HBM byte counters)")
+    ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--tune-cache", default="", help="JSON cache of the batch autotuner")
     args = ap.parse_args()
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has no "
               "multi-GPU path. Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batch4096":
+        return run_batch(args)
 
     import numpy as np
     import torch

@@ -270,14 +270,19 @@ class Batch:
     a graph), build() does both.  items: list of (d_text, n, sym_bytes, L,
     kind, Structure)."""
 
+    @staticmethod
+    def item_array(items):
+        arr = (WtBatchItem * len(items))()
+        for i, (t, n, b, L, kind, s) in enumerate(items):
+            arr[i] = WtBatchItem(ctypes.c_void_p(t.data_ptr() if n > 0 else s.buf.data_ptr()), n, b, L,
+                                 kind, 0, ctypes.pointer(s.view))
+        return arr
+
     def __init__(self, items, tune=None, ws=None):
         torch = _torch()
         self.items = items
         self.tune = tune
-        self.arr = (WtBatchItem * len(items))()
-        for i, (t, n, b, L, kind, s) in enumerate(items):
-            self.arr[i] = WtBatchItem(ctypes.c_void_p(t.data_ptr() if n > 0 else s.buf.data_ptr()), n, b,
-                                      L, kind, 0, ctypes.pointer(s.view))
+        self.arr = Batch.item_array(items)
         need = int(wt_batch_workspace_bytes(self.arr, len(items), _tune_ptr(tune)))
         if need == 0:
             raise WtError(WT_EINVAL, "wt_batch_workspace_bytes")
