@@ -158,9 +158,9 @@ const char *wt_strerror(int code);
  * whose kernels loop over the work items of every text (with tune->persist
  * set, a fixed number of workgroups loops over all items: a persistent grid).
  * d_ws: workspace of wt_batch_workspace_bytes(items, count, tune) bytes.
- *   wt_batch_prepare  writes the per-text descriptors and work-item tables
- *                     into the workspace with a synchronous host-to-device
- *                     copy (host call; waits for `stream`).
+ *   wt_batch_prepare  copies the per-text descriptors and work-item tables
+ *                     into the workspace on `stream` and waits for `stream`
+ *                     (host call; the copy is done when it returns).
  *   wt_batch_launch   enqueues the kernels only (no host copies, no memset):
  *                     capturable in a HIP graph and replayable, provided the
  *                     items and workspace are those of the last prepare.

@@ -543,9 +543,12 @@ static int batch_prepare(const wt_batch_item *items, uint32_t count, void *d_ws,
     int rc = batch_image(items, count, d_ws, ws_bytes, tune, bi);
     if (rc != WT_OK) return rc;
     uint8_t *base = (uint8_t *)align_up((uintptr_t)d_ws, 256);
-    if (hipStreamSynchronize(stream) != hipSuccess) return WT_EHIP;
-    if (hipMemcpy(base, bi.img.data(), bi.img.size(), hipMemcpyHostToDevice) != hipSuccess)
+    // on the caller's stream, so that the copy waits for nothing else; the
+    // host image lives until the stream has passed it
+    if (hipMemcpyAsync(base, bi.img.data(), bi.img.size(), hipMemcpyHostToDevice, stream) !=
+        hipSuccess)
         return WT_EHIP;
+    if (hipStreamSynchronize(stream) != hipSuccess) return WT_EHIP;
     return WT_OK;
 }
 
