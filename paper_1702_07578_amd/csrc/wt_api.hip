@@ -101,10 +101,8 @@ static int plan_text(uint64_t n, uint32_t b, uint32_t L, uint32_t kind, const wt
     const uint32_t target = (tune && tune->grid) ? tune->grid : kTargetRanges;
     d.R = (uint32_t)std::max<uint64_t>(1, cdiv64(d.ntiles, target));
     d.nranges = (uint32_t)cdiv64(d.ntiles, d.R);
-    uint32_t ch = 1;
-    while ((uint64_t)ch * ch < d.nranges) ch <<= 1;
-    d.CH = ch;
-    d.nchunks = (uint32_t)cdiv64(d.nranges, ch);
+    d.CH = kBorderChunk;
+    d.nchunks = (uint32_t)cdiv64(d.nranges, d.CH);
     d.W = words_per_level(n);
     d.nb = d.W / 8;
     d.rank_stride = rank_stride(n);
@@ -640,10 +638,9 @@ int wt_build_profiled(wt_kind kind, const void *d_text, uint64_t n, uint32_t sym
 
 const char *wt_kernel_name(uint32_t id)
 {
-    static const char *names[] = {"init",        "hist",         "chunk_sum", "key_scan",
-                                  "tile_prefix", "zero_borders", "scatter",   "dir_count",
-                                  "dir_scan",    "dir_write",    "walk",      "gather",
-                                  "query"};
+    static const char *names[] = {"init",      "hist",      "chunk_sum", "borders",
+                                  "scatter",   "dir_count", "dir_scan",  "dir_write",
+                                  "walk",      "gather",    "query"};
     return id < sizeof(names) / sizeof(names[0]) ? names[id] : "unknown";
 }
 

@@ -132,12 +132,14 @@ __global__ __launch_bounds__(kTileThreads) void k_hist(const TextDesc *__restric
 }
 
 // ---------------------------------------------------------------------------
-// K1a: per chunk of ranges, column sums of the range histograms
+// K1a: per chunk of kBorderChunk ranges, column sums of the range histograms
+// (several threads per key when the keys are fewer than the threads)
 
 __global__ __launch_bounds__(256) void k_chunk_sum(const TextDesc *__restrict__ descs,
                                                    const uint32_t *__restrict__ bases, uint32_t nd,
                                                    uint32_t nitems, uint32_t g)
 {
+    __shared__ uint32_t part[256];
     for (uint32_t item = blockIdx.x; item < nitems; item += gridDim.x) {
         const uint32_t ti = find_text(bases, nd, item);
         const TextDesc &d = descs[ti];
@@ -145,89 +147,53 @@ __global__ __launch_bounds__(256) void k_chunk_sum(const TextDesc *__restrict__ 
         if (g >= d.G || c >= d.nchunks) continue;
         const uint32_t Kg = group_bits(d, g);
         if (Kg == 0) continue;
-        const uint32_t nk = 1u << Kg;
-        const uint32_t t0 = c * d.CH, t1 = min(d.nranges, t0 + d.CH);
-        for (uint32_t k = threadIdx.x; k < nk; k += blockDim.x) {
-            uint32_t s = 0;
-            for (uint32_t t = t0; t < t1; t++) s += d.H[(uint64_t)t * nk + k];
+        const uint32_t nk = 1u << Kg, P = blockDim.x / nk;  // parts per key (>= 1)
+        const uint32_t k = threadIdx.x % nk, p = threadIdx.x / nk;
+        const uint32_t r0 = c * d.CH, r1 = min(d.nranges, r0 + d.CH);
+        uint32_t s = 0;
+        if (p < P)
+            for (uint32_t r = r0 + p; r < r1; r += P) s += d.H[(uint64_t)r * nk + k];
+        part[threadIdx.x] = s;
+        __syncthreads();
+        if (p == 0) {
+            for (uint32_t q = 1; q < P; q++) s += part[q * nk + k];
             d.CS[(uint64_t)c * nk + k] = s;
         }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// K1b: per text, chunk prefixes, key totals of every group level (merged
-// upward), key bases in prefix and reversed order, Z, and for a deep WT the
-// first row of the interval walk.
-
-__global__ __launch_bounds__(256) void k_key_scan(const TextDesc *__restrict__ descs, uint32_t nd,
-                                                  uint32_t g)
-{
-    const TextDesc &d = descs[blockIdx.x];
-    if (g >= d.G) return;
-    const uint32_t Kg = group_bits(d, g);
-    if (Kg == 0) return;
-    const uint32_t nk = 1u << Kg;
-    const uint32_t tid = threadIdx.x;
-    // chunk prefixes and totals of the deepest group level
-    for (uint32_t k = tid; k < nk; k += blockDim.x) {
-        uint32_t run = 0;
-        for (uint32_t c = 0; c < d.nchunks; c++) {
-            uint32_t x = d.CS[(uint64_t)c * nk + k];
-            d.CS[(uint64_t)c * nk + k] = run;
-            run += x;
-        }
-        d.HT[lvl_off(Kg) + k] = run;
-    }
-    __syncthreads();
-    // merge upward: totals of every shorter key
-    for (uint32_t a = Kg; a-- > 0;) {
-        for (uint32_t k = tid; k < (1u << a); k += blockDim.x)
-            d.HT[lvl_off(a) + k] = d.HT[lvl_off(a + 1) + 2 * k] + d.HT[lvl_off(a + 1) + 2 * k + 1];
         __syncthreads();
     }
-    // key bases per level, one thread per (level, order)
-    if (tid < 2 * (Kg + 1)) {
-        const uint32_t a = tid >> 1;
-        const bool rev = tid & 1;
-        const uint32_t *ht = d.HT + lvl_off(a);
-        uint32_t *kb = (rev ? d.KBpi : d.KBid) + lvl_off(a);
-        uint32_t run = 0;
-        for (uint32_t i = 0; i < (1u << a); i++) {
-            uint32_t k = rev ? rev_bits(i, a) : i;
-            kb[k] = run;
-            run += ht[k];
-        }
-    }
-    // Z of the group's levels: zeros of level a = symbols whose next bit is 0,
-    // i.e. the even keys one level deeper (Section 5.1)
-    if (tid < Kg) {
-        const uint32_t a = tid;
-        const uint32_t *ht = d.HT + lvl_off(a + 1);
-        uint64_t z = 0;
-        for (uint32_t k = 0; k < (2u << a); k += 2) z += ht[k];
-        d.zeros[g * d.K + a] = z;
-    }
-    __syncthreads();
-    // deep WT: intervals of the K-bit prefixes (level K) seed the walk
-    if (d.kind == WT_TREE && d.G > 1 && g == 0) {
-        const uint32_t np = 1u << d.K;
-        uint32_t *tab = d.walk;  // walk_off(K, K) == 0
-        for (uint32_t p = tid; p < np; p += blockDim.x) {
-            tab[p] = d.KBpi[lvl_off(Kg) + p];
-            tab[np + p] = d.HT[lvl_off(Kg) + p];
-            tab[2 * np + p] = d.KBid[lvl_off(Kg) + p];
-        }
-    }
 }
 
 // ---------------------------------------------------------------------------
-// K1c: per chunk, range-exclusive prefix of every column
+// K1b: per chunk of ranges, everything the scatter needs before it starts
+// (Algorithm 1: merged histograms and borders; Section 3.2: borders
+// interleaved over slices; Section 5.1: bit-reversed order and Z):
+//   - the chunk's prefix and the totals of every finest key, from all chunk sums
+//   - totals of every shorter key (merged upward) and the key bases of every
+//     level in prefix and in bit-reversed order (computed by every block; the
+//     text's first block also publishes them, with Z and, for a deep WT, the
+//     first row of the interval walk)
+//   - TP, the range-exclusive prefix of every finest key for the chunk's ranges
+//   - the output words shared between ranges: a range's run of key k on a
+//     level starts at G (the subtree sum of TP plus the key's base); when G is
+//     not word-aligned its word also holds bits of the previous range (or
+//     key), both sides fill it by atomic OR, and it is cleared here; the
+//     text's first range also clears the padding words.
 
-__global__ __launch_bounds__(256) void k_tile_prefix(const TextDesc *__restrict__ descs,
-                                                     const uint32_t *__restrict__ bases,
-                                                     uint32_t nd, uint32_t nitems, uint32_t g)
+constexpr uint32_t kBorderThreads = 1024;
+constexpr uint32_t kBorderWaves = kBorderThreads / 64;
+
+__global__ __launch_bounds__(kBorderThreads) void k_borders(const TextDesc *__restrict__ descs,
+                                                            const uint32_t *__restrict__ bases,
+                                                            uint32_t nd, uint32_t nitems,
+                                                            uint32_t g)
 {
+    constexpr uint32_t kK = 1u << kMaxGroupBits;
+    __shared__ uint32_t part[kBorderThreads];
+    __shared__ uint32_t pre[kK];
+    __shared__ uint32_t tot[2 * kK];
+    __shared__ uint32_t kbid[2 * kK], kbpi[2 * kK];
+    __shared__ uint32_t S[kBorderWaves][kK + 1];
+    const uint32_t tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     for (uint32_t item = blockIdx.x; item < nitems; item += gridDim.x) {
         const uint32_t ti = find_text(bases, nd, item);
         const TextDesc &d = descs[ti];
@@ -235,51 +201,120 @@ __global__ __launch_bounds__(256) void k_tile_prefix(const TextDesc *__restrict_
         if (g >= d.G || c >= d.nchunks) continue;
         const uint32_t Kg = group_bits(d, g);
         if (Kg == 0) continue;
-        const uint32_t nk = 1u << Kg;
-        const uint32_t t0 = c * d.CH, t1 = min(d.nranges, t0 + d.CH);
-        for (uint32_t k = threadIdx.x; k < nk; k += blockDim.x) {
-            uint32_t run = d.CS[(uint64_t)c * nk + k];
-            for (uint32_t t = t0; t < t1; t++) {
-                uint32_t x = d.H[(uint64_t)t * nk + k];
-                d.TP[(uint64_t)t * nk + k] = run;
-                run += x;
+        const uint32_t nk = 1u << Kg, P = kBorderThreads / nk;
+        const uint32_t k = tid % nk, p = tid / nk;
+
+        // chunk prefix and totals of the finest keys
+        uint32_t before = 0, all = 0;
+        for (uint32_t c2 = p; c2 < d.nchunks; c2 += P) {
+            const uint32_t x = d.CS[(uint64_t)c2 * nk + k];
+            all += x;
+            if (c2 < c) before += x;
+        }
+        part[tid] = before;
+        __syncthreads();
+        if (p == 0) {
+            for (uint32_t q = 1; q < P; q++) before += part[q * nk + k];
+            pre[k] = before;
+        }
+        __syncthreads();
+        part[tid] = all;
+        __syncthreads();
+        if (p == 0) {
+            for (uint32_t q = 1; q < P; q++) all += part[q * nk + k];
+            tot[lvl_off(Kg) + k] = all;
+        }
+        __syncthreads();
+        for (uint32_t a = Kg; a-- > 0;) {
+            for (uint32_t kk = tid; kk < (1u << a); kk += kBorderThreads)
+                tot[lvl_off(a) + kk] = tot[lvl_off(a + 1) + 2 * kk] + tot[lvl_off(a + 1) + 2 * kk + 1];
+            __syncthreads();
+        }
+        // key bases: one wave per (level, order), keys visited in that order
+        for (uint32_t job = w; job < 2 * (Kg + 1); job += kBorderWaves) {
+            const uint32_t a = job >> 1;
+            const bool rev = job & 1;
+            uint32_t *kb = (rev ? kbpi : kbid) + lvl_off(a);
+            const uint32_t *ht = tot + lvl_off(a);
+            uint32_t carry = 0;
+            for (uint32_t base = 0; base < (1u << a); base += 64) {
+                const uint32_t i = base + lane;
+                const uint32_t key = (i < (1u << a)) ? (rev ? rev_bits(i, a) : i) : 0u;
+                const uint32_t x = (i < (1u << a)) ? ht[key] : 0u;
+                const uint32_t incl = wave_incl_scan(x);
+                if (i < (1u << a)) kb[key] = carry + incl - x;
+                carry += last_lane(incl);
             }
         }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// K1d: clear the output words shared between ranges: a range's runs of key k
-// start at G (its first tile's interval start); when G is not word-aligned
-// the word holding G also holds bits of the previous range (or the previous
-// key) and both sides fill it by atomic OR.  Also clears the padding words.
-
-__global__ __launch_bounds__(kTileThreads) void k_zero_borders(const TextDesc *__restrict__ descs,
-                                                               const uint32_t *__restrict__ bases,
-                                                               uint32_t nd, uint32_t nitems,
-                                                               uint32_t g)
-{
-    __shared__ uint32_t G[kTab];
-    for (uint32_t item = blockIdx.x; item < nitems; item += gridDim.x) {
-        const uint32_t ti = find_text(bases, nd, item);
-        const TextDesc &d = descs[ti];
-        const uint32_t r = item - item_base(bases, nd, ti);
-        if (g >= d.G || r >= d.nranges) continue;
-        const uint32_t Kg = group_bits(d, g);
-        if (Kg == 0) continue;
-        range_start_G(d, g, Kg, r, G);
-        for (uint32_t e = threadIdx.x; e < lvl_off(Kg); e += kTileThreads) {
-            const uint32_t a = 31 - __clz(e + 1);  // level of table entry e
-            const uint32_t gs = G[e];
-            if ((gs & 63) != 0) level_ptr(d, g, a)[gs >> 6] = 0;
+        __syncthreads();
+        if (c == 0) {
+            for (uint32_t e = tid; e < lvl_off(Kg + 1); e += kBorderThreads) {
+                d.HT[e] = tot[e];
+                d.KBid[e] = kbid[e];
+                d.KBpi[e] = kbpi[e];
+            }
+            // Z of the group's levels: zeros of level a = symbols whose next
+            // bit is 0, the even keys one level deeper (Section 5.1)
+            if (tid < Kg) {
+                uint64_t z = 0;
+                for (uint32_t kk = 0; kk < (2u << tid); kk += 2) z += tot[lvl_off(tid + 1) + kk];
+                d.zeros[g * d.K + tid] = z;
+            }
+            // deep WT: intervals of the K-bit prefixes (level K) seed the walk
+            if (d.kind == WT_TREE && d.G > 1 && g == 0) {
+                uint32_t *tab = d.walk;  // walk_off(K, K) == 0
+                for (uint32_t q = tid; q < nk; q += kBorderThreads) {
+                    tab[q] = kbpi[lvl_off(Kg) + q];
+                    tab[nk + q] = tot[lvl_off(Kg) + q];
+                    tab[2 * nk + q] = kbid[lvl_off(Kg) + q];
+                }
+            }
         }
-        if (r == 0) {
-            // padding words, and the word holding position n (its bits past n
-            // must stay zero; the run ending there fills it by atomic OR)
-            const uint64_t first = d.n >> 6;
-            for (uint32_t a = 0; a < Kg; a++) {
-                uint64_t *out = level_ptr(d, g, a);
-                for (uint64_t wd = first + threadIdx.x; wd < d.W; wd += kTileThreads) out[wd] = 0;
+        // TP of the chunk's ranges: each part of a key takes consecutive ranges
+        const uint32_t r0 = c * d.CH, r1 = min(d.nranges, r0 + d.CH);
+        const uint32_t per = (d.CH + P - 1) / P;
+        const uint32_t q0 = min(r1, r0 + p * per), q1 = min(r1, q0 + per);
+        uint32_t s = 0;
+        for (uint32_t r = q0; r < q1; r++) s += d.H[(uint64_t)r * nk + k];
+        part[tid] = s;
+        __syncthreads();
+        uint32_t run = pre[k];
+        for (uint32_t q = 0; q < p; q++) run += part[q * nk + k];
+        for (uint32_t r = q0; r < q1; r++) {
+            const uint32_t x = d.H[(uint64_t)r * nk + k];
+            d.TP[(uint64_t)r * nk + k] = run;
+            run += x;
+        }
+        __syncthreads();
+        // shared words of every range of the chunk (one wave per range)
+        for (uint32_t r = r0 + w; r < r1; r += kBorderWaves) {
+            const uint32_t *tp = d.TP + (uint64_t)r * nk;
+            uint32_t *sw = S[w];
+            uint32_t carry = 0;
+            for (uint32_t base = 0; base < nk; base += 64) {
+                const uint32_t j = base + lane;
+                const uint32_t x = (j < nk) ? tp[j] : 0u;
+                const uint32_t incl = wave_incl_scan(x);
+                if (j < nk) sw[j] = carry + incl - x;
+                carry += last_lane(incl);
+            }
+            if (lane == 0) sw[nk] = carry;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (uint32_t e = lane; e < lvl_off(Kg); e += 64) {
+                const uint32_t a = 31 - __clz(e + 1), kk = e - lvl_off(a), sh = Kg - a;
+                const uint32_t *kb = use_prefix_order(d, g, a, Kg) ? kbid : kbpi;
+                const uint32_t gs = sw[(kk + 1) << sh] - sw[kk << sh] + kb[e];
+                if ((gs & 63) != 0 && (gs >> 6) < d.W) level_ptr(d, g, a)[gs >> 6] = 0;
+            }
+            if (r == 0) {
+                // padding words, and the word holding position n (its bits
+                // past n must stay zero; the run ending there fills it by OR)
+                for (uint32_t a = 0; a < Kg; a++) {
+                    uint64_t *out = level_ptr(d, g, a);
+                    for (uint64_t wd = (d.n >> 6) + lane; wd < d.W; wd += 64) out[wd] = 0;
+                }
             }
         }
         __syncthreads();
@@ -411,14 +446,9 @@ hipError_t launch_group(const TextDesc *d_descs, const GroupLaunch &gl, const La
     hipLaunchKernelGGL(k_chunk_sum, dim3(grid_for(gl.nchunks, gl.grid_cap)), dim3(256), 0,
                        ctx.stream, d_descs, gl.chunk_bases, nd, gl.nchunks, g);
     after(ctx, KID_CHUNK_SUM);
-    hipLaunchKernelGGL(k_key_scan, dim3(nd), dim3(256), 0, ctx.stream, d_descs, nd, g);
-    after(ctx, KID_KEY_SCAN);
-    hipLaunchKernelGGL(k_tile_prefix, dim3(grid_for(gl.nchunks, gl.grid_cap)), dim3(256), 0,
+    hipLaunchKernelGGL(k_borders, dim3(grid_for(gl.nchunks, gl.grid_cap)), dim3(kBorderThreads), 0,
                        ctx.stream, d_descs, gl.chunk_bases, nd, gl.nchunks, g);
-    after(ctx, KID_TILE_PREFIX);
-    hipLaunchKernelGGL(k_zero_borders, dim3(grid_for(gl.nranges, gl.grid_cap)), dim3(kTileThreads),
-                       0, ctx.stream, d_descs, gl.range_bases, nd, gl.nranges, g);
-    after(ctx, KID_ZERO_BORDERS);
+    after(ctx, KID_BORDERS);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_scatter(d_descs, gl, ctx);

@@ -23,6 +23,8 @@ constexpr uint32_t kMaxGroupBits = 8;
 // Ranges per text when the text is long enough: four per resident scatter
 // wave (12 per CU on 256 CUs), so that the last round of ranges is short.
 constexpr uint32_t kTargetRanges = 12288;
+// Ranges per chunk of the column scans over the range histograms.
+constexpr uint32_t kBorderChunk = 32;
 // Directory: 512-bit blocks, chunks of kDirChunk blocks per workgroup.
 constexpr uint32_t kDirChunk = 1024;
 
@@ -96,9 +98,7 @@ enum KernelId : uint32_t {
     KID_INIT = 0,
     KID_HIST,
     KID_CHUNK_SUM,
-    KID_KEY_SCAN,
-    KID_TILE_PREFIX,
-    KID_ZERO_BORDERS,
+    KID_BORDERS,
     KID_SCATTER,
     KID_DIR_COUNT,
     KID_DIR_SCAN,
