@@ -48,19 +48,22 @@ __global__ void k_init_batch(const TextDesc *__restrict__ descs, uint32_t nd)
 // Each lane reads 16-byte units of the range; units past the range end are
 // read symbol by symbol.
 
+constexpr uint32_t kHistCopies = 8;
+
+// himask: the bits at or above L of every symbol in a 32-bit word (0 when no
+// check is needed); key of a symbol: its bits from `shift` up, kw of them
+// (the key's bits above the symbol's width are zero)
 template <typename E>
-__device__ inline void count_unit(const uint4 &u, uint32_t shift, uint32_t mask, uint32_t L,
-                                  bool check, bool &bad, uint32_t *hist)
+__device__ inline void count_unit(const uint4 &u, uint32_t shift, uint32_t kw, uint32_t himask,
+                                  bool &bad, uint32_t *hist)
 {
     const uint32_t w4[4] = {u.x, u.y, u.z, u.w};
 #pragma unroll
     for (uint32_t q = 0; q < 4; q++) {
+        bad |= (w4[q] & himask) != 0;
 #pragma unroll
-        for (uint32_t s = 0; s < 4 / sizeof(E); s++) {
-            const uint32_t e = (sizeof(E) == 4) ? w4[q] : ((w4[q] >> (s * 8 * sizeof(E))) & ((1u << (8 * sizeof(E))) - 1u));
-            if (check && (e >> L) != 0) bad = true;
-            atomicAdd(&hist[(e >> shift) & mask], 1u);
-        }
+        for (uint32_t s = 0; s < 4 / sizeof(E); s++)
+            atomicAdd(&hist[__builtin_amdgcn_ubfe(w4[q], s * 8 * sizeof(E) + shift, kw) * kHistCopies], 1u);
     }
 }
 
@@ -69,17 +72,31 @@ __device__ void hist_range(const TextDesc &d, uint32_t g, uint32_t Kg, uint32_t 
 {
     const uint32_t tid = threadIdx.x, w = tid >> 6;
     const uint32_t nk = 1u << Kg, mask = nk - 1u;
+    // every wave counts into kHistCopies interleaved copies (copy = lane mod
+    // kHistCopies), so lanes with equal keys mostly hit different words in
+    // different banks
     const uint32_t shift = d.L - g * d.K - Kg;
     const uint64_t span = (uint64_t)d.R << d.log2S;
     const uint64_t start = (uint64_t)r * span;
     const uint64_t len = min(span, d.n - start);
     const E *src = (const E *)seq_in(d, g) + start;
-    uint32_t *hist = sh + w * nk;
+    uint32_t *hist = sh + w * nk * kHistCopies + (tid & (kHistCopies - 1));
 
-    for (uint32_t i = tid; i < kTileWaves * nk; i += kTileThreads) sh[i] = 0;
+    for (uint32_t i = tid; i < kTileWaves * nk * kHistCopies; i += kTileThreads) sh[i] = 0;
     __syncthreads();
     bool bad = false;
     const bool check = (g == 0) && (d.L < 32);
+    // bits at or above L of every symbol of a 32-bit word
+    // key bits that lie inside the symbol (a key may reach above its width)
+    const uint32_t width = 8 * sizeof(E);
+    const uint32_t kw = shift >= width ? 0u : min(Kg, width - shift);
+    const uint32_t kshift = shift >= width ? 0u : shift;
+    uint32_t himask = 0;
+    if (check && d.L < 8 * sizeof(E)) {
+        const uint32_t one = (sizeof(E) == 4) ? 0xFFFFFFFFu : ((1u << (8 * sizeof(E))) - 1u);
+        const uint32_t m = one & ~((1u << d.L) - 1u);
+        himask = (sizeof(E) == 1) ? m * 0x01010101u : (sizeof(E) == 2 ? m * 0x00010001u : m);
+    }
     const uint32_t per_unit = 16 / sizeof(E);
     uint64_t done = 0;
     if (((uintptr_t)src & 15) == 0) {
@@ -89,18 +106,18 @@ __device__ void hist_range(const TextDesc &d, uint32_t g, uint32_t Kg, uint32_t 
         for (; i + 3 * kTileThreads < nu; i += 4 * kTileThreads) {
             const uint4 a0 = u[i], a1 = u[i + kTileThreads], a2 = u[i + 2 * kTileThreads],
                         a3 = u[i + 3 * kTileThreads];
-            count_unit<E>(a0, shift, mask, d.L, check, bad, hist);
-            count_unit<E>(a1, shift, mask, d.L, check, bad, hist);
-            count_unit<E>(a2, shift, mask, d.L, check, bad, hist);
-            count_unit<E>(a3, shift, mask, d.L, check, bad, hist);
+            count_unit<E>(a0, kshift, kw, himask, bad, hist);
+            count_unit<E>(a1, kshift, kw, himask, bad, hist);
+            count_unit<E>(a2, kshift, kw, himask, bad, hist);
+            count_unit<E>(a3, kshift, kw, himask, bad, hist);
         }
-        for (; i < nu; i += kTileThreads) count_unit<E>(u[i], shift, mask, d.L, check, bad, hist);
+        for (; i < nu; i += kTileThreads) count_unit<E>(u[i], kshift, kw, himask, bad, hist);
         done = nu * per_unit;
     }
     for (uint64_t i = done + tid; i < len; i += kTileThreads) {
         const uint32_t e = src[i];
         if (check && (e >> d.L) != 0) bad = true;
-        atomicAdd(&hist[(e >> shift) & mask], 1u);
+        atomicAdd(&hist[((e >> shift) & mask) * kHistCopies], 1u);
     }
     if (bad) atomicExch(d.status, (int32_t)WT_ERANGE);
     __syncthreads();
@@ -108,7 +125,9 @@ __device__ void hist_range(const TextDesc &d, uint32_t g, uint32_t Kg, uint32_t 
     for (uint32_t k = tid; k < nk; k += kTileThreads) {
         uint32_t s = 0;
 #pragma unroll
-        for (uint32_t ww = 0; ww < kTileWaves; ww++) s += sh[ww * nk + k];
+        for (uint32_t ww = 0; ww < kTileWaves; ww++)
+#pragma unroll
+            for (uint32_t cp = 0; cp < kHistCopies; cp++) s += sh[(ww * nk + k) * kHistCopies + cp];
         H[k] = s;
     }
 }
@@ -117,7 +136,7 @@ __global__ __launch_bounds__(kTileThreads) void k_hist(const TextDesc *__restric
                                                        const uint32_t *__restrict__ bases,
                                                        uint32_t nd, uint32_t nitems, uint32_t g)
 {
-    __shared__ uint32_t sh[kTileWaves * (1u << kMaxGroupBits)];
+    __shared__ uint32_t sh[kTileWaves * (1u << kMaxGroupBits) * kHistCopies];
     for (uint32_t item = blockIdx.x; item < nitems; item += gridDim.x) {
         const uint32_t ti = find_text(bases, nd, item);
         const TextDesc &d = descs[ti];
