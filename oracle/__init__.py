@@ -68,6 +68,7 @@ def _bind(lib):
         "orc_queries_walk": (_int, [_int, _u64p, _u64, _u64p, _u64, _u32, _int, _u32p, _u64p,
                                     _u64, _u64p]),
         "orc_sample_level": (_int, [_int, _vp, _u64, _u32, _u32, _u32, _u64p, _u64, _u8p]),
+        "orc_map_wt_to_wm": (_int, [_vp, _u64, _u32, _u32, _u32, _u64p, _u64, _u64p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -187,6 +188,17 @@ class Oracle:
         if rc != OK:
             raise OracleError(rc, "queries_walk")
         return out[: a.size]
+
+    def map_wt_to_wm(self, text, L: int, level: int, positions):
+        """Positions in WM level `level` of the bits at the given WT positions."""
+        t, b = self._text(text)
+        p = np.ascontiguousarray(positions, dtype=np.uint64)
+        out = np.zeros(max(p.size, 1), dtype=np.uint64)
+        rc = self.lib.orc_map_wt_to_wm(t.ctypes.data, t.size, b, L, level, self._p(p, _u64p), p.size,
+                                       self._p(out, _u64p))
+        if rc != OK:
+            raise OracleError(rc, "map_wt_to_wm")
+        return out[: p.size]
 
     def sample_level(self, kind: int, text, L: int, level: int, positions):
         t, b = self._text(text)

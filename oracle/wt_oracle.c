@@ -558,3 +558,53 @@ done:
     free(req);
     return rc;
 }
+
+/* ---- position of a WT bit in the WM (Section 5.1; Lemma 5) -------------- */
+
+/* Level `level` of the WT and of the WM hold the same intervals (one per
+ * level-bit prefix, same size, same content in the same order), the WT's in
+ * prefix order and the WM's in bit-reversed prefix order.  Position i of WT
+ * level `level` lies in the interval of prefix bp (the prefix whose WT
+ * interval contains i), at offset i - SPos_WT[bp]; the same bit sits at
+ * SPos_WM[bp] + that offset in the WM.  Computed here from the direct counts. */
+int orc_map_wt_to_wm(const void *text, uint64_t n, uint32_t sym_bytes, uint32_t L, uint32_t level,
+                     const uint64_t *positions, uint64_t m, uint64_t *out)
+{
+    if (level >= L || level > 26) return ORC_EINVAL;
+    uint64_t keys = (uint64_t)1 << level;
+    uint64_t *hist = (uint64_t *)malloc(keys * sizeof(uint64_t));
+    uint64_t *swt = (uint64_t *)malloc(keys * sizeof(uint64_t));
+    uint64_t *swm = (uint64_t *)malloc(keys * sizeof(uint64_t));
+    int rc = ORC_OK;
+    if (!hist || !swt || !swm) {
+        rc = ORC_ENOMEM;
+        goto done;
+    }
+    if ((rc = orc_hist(text, n, sym_bytes, L, level, hist)) != ORC_OK) goto done;
+    orc_spos(ORC_WT, hist, level, swt);
+    orc_spos(ORC_WM, hist, level, swm);
+    for (uint64_t q = 0; q < m; q++) {
+        uint64_t i = positions[q];
+        if (i >= n) {
+            rc = ORC_EINVAL;
+            goto done;
+        }
+        /* bp: the last prefix whose interval starts at or before i (WT
+         * starts do not decrease with the prefix; an empty interval shares
+         * its start with the next one, so the last such prefix is never
+         * empty) */
+        uint64_t lo = 0, hi = keys;
+        while (hi - lo > 1) {
+            uint64_t mid = (lo + hi) / 2;
+            if (swt[mid] <= i) lo = mid;
+            else hi = mid;
+        }
+        out[q] = swm[lo] + (i - swt[lo]);
+    }
+done:
+    free(hist);
+    free(swt);
+    free(swm);
+    return rc;
+}
+

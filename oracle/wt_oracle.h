@@ -50,6 +50,10 @@ int orc_queries_walk(int kind, const uint64_t *bits, uint64_t W, const uint64_t 
                      uint64_t n, uint32_t L, int op, const uint32_t *syms, const uint64_t *args,
                      uint64_t m, uint64_t *out);
 
+/* position in WM level `level` of the bit at WT position positions[q] */
+int orc_map_wt_to_wm(const void *text, uint64_t n, uint32_t sym_bytes, uint32_t L, uint32_t level,
+                     const uint64_t *positions, uint64_t m, uint64_t *out);
+
 /* bit `level` of the WT/WM at the given positions (0/1 per position) */
 int orc_sample_level(int kind, const void *text, uint64_t n, uint32_t sym_bytes, uint32_t L,
                      uint32_t level, const uint64_t *positions, uint64_t m, uint8_t *out);

@@ -348,6 +348,30 @@ def check_sample_level(o):
                 assert [int(x) for x in got] == want
 
 
+def check_map_wt_to_wm(o):
+    """The WT-to-WM position map (Section 5.1, Lemma 5): the hand-worked
+    running example, identity on levels 0 and 1, a bijection on every level,
+    and it carries every WT bit to an equal WM bit."""
+    g = read_golden()
+    T = np.array([int(x) for x in g["text"].split()], dtype=np.uint8)
+    got = o.map_wt_to_wm(T, 3, 2, np.arange(T.size))
+    assert [int(x) for x in got] == [int(x) for x in g["map_wt_to_wm2"].split()]
+    rng = np.random.default_rng(23)
+    for L, n in ((2, 100), (3, 500), (5, 2000), (8, 3000), (11, 1500)):
+        T = rng.integers(0, 1 << L, size=n, dtype=np.uint64).astype(np.uint16)
+        if L == 11:  # a skewed text with empty intervals
+            T = (T % 37) * 53 % (1 << L)
+        wt, _ = o.build(WT, T, L)
+        wm, _ = o.build(WM, T, L)
+        for l in range(L):
+            j = o.map_wt_to_wm(T, L, l, np.arange(n))
+            if l <= 1:
+                assert np.array_equal(j, np.arange(n, dtype=np.uint64))
+            assert np.array_equal(np.sort(j), np.arange(n, dtype=np.uint64)), (L, l)
+            bt, bm = unpack(wt[l], n), unpack(wm[l], n)
+            assert all(bt[i] == bm[int(j[i])] for i in range(n)), (L, l)
+
+
 def check_errors(o):
     import oracle
     T = np.array([0, 1, 8], dtype=np.uint8)
@@ -365,4 +389,4 @@ def check_errors(o):
 
 ALL_CHECKS = [check_golden, check_printed_small_facts, check_levels_brute, check_wide_symbols,
               check_invariants, check_queries, check_rank_select_bv, check_directory,
-              check_sample_level, check_errors]
+              check_sample_level, check_map_wt_to_wm, check_errors]

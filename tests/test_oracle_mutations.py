@@ -50,6 +50,10 @@ MUTATIONS = {
     "no_range_check": ("if (L < 32 && (a >> L) != 0) return ORC_ERANGE;", "(void)a;"),
     # WT rank walk maps the zero child with the wrong base
     "walk_wt_rank_base": ("p = s + orc_rank_bv(lv, p, 0) - r0s;", "p = orc_rank_bv(lv, p, 0) - r0s;"),
+    # position map takes the WM start from the WT order
+    "map_wm_start_from_wt": ("out[q] = swm[lo] + (i - swt[lo]);", "out[q] = swt[lo] + (i - swt[lo]);"),
+    # position map searches with the WM starts
+    "map_search_wm_order": ("if (swt[mid] <= i) lo = mid;", "if (swm[mid] <= i) lo = mid;"),
     # WM select walk forgets the Z offset
     "walk_wm_select_z": ("p = b ? orc_select_bv(lv, n, p - zeros[l] + 1, 1)", "p = b ? orc_select_bv(lv, n, p + 1, 1)"),
 }
