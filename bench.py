@@ -434,6 +434,46 @@ def main():
     torch.cuda.synchronize()
     q_per_s = 6 * m / (qe0.elapsed_time(qe1) / 1e3)
 
+    # conversion between the two structures (Section 5.1) and the Lemma 5
+    # position map, on the measured outputs: each converted structure must
+    # equal the one built directly
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0e, t1e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0e.record()
+        r = fn()
+        t1e.record()
+        torch.cuda.synchronize()
+        return r, t0e.elapsed_time(t1e)
+
+    def same_levels(a, b):
+        Wd = a.view.words_per_level
+        return torch.equal(a.buf[: L * Wd * 8], b.buf[: L * Wd * 8])
+
+    conv = {}
+    for k_from, name in ((B.WT_MATRIX, "wm_to_wt_ms"), (B.WT_TREE, "wt_to_wm_ms")):
+        other, ms = timed(lambda: B.convert(structs[k_from]))
+        if not same_levels(other, structs[1 - k_from]) or other.status() != 0:
+            raise SystemExit(f"conversion from kind {k_from} differs from the direct build")
+        conv[name] = round(ms, 3)
+        del other
+    pm, pm_ms = timed(lambda: B.PosMap(structs[B.WT_TREE]))
+    lvl = L - 1
+    _, pq_ms = timed(lambda: pm.query(lvl, qpos))
+    j = pm.query(lvl, qpos)
+    wt_words = structs[B.WT_TREE].buf[: L * W * 8].view(torch.int64).view(L, W)[lvl]
+    wm_words = structs[B.WT_MATRIX].buf[: L * W * 8].view(torch.int64).view(L, W)[lvl]
+    bit_wt = (wt_words[qpos >> 6] >> (qpos & 63)) & 1
+    bit_wm = (wm_words[j >> 6] >> (j & 63)) & 1
+    if not torch.equal(bit_wt, bit_wm):
+        raise SystemExit("position map does not carry WT bits to equal WM bits")
+    # both structures when both are wanted: build the WM, convert it to the WT
+    conv["wm_build_plus_convert_ms"] = round(ms_per_step / 2 + conv["wm_to_wt_ms"], 3)
+    conv["posmap_build_ms"] = round(pm_ms, 3)
+    conv["posmap_queries_per_s"] = round(m / (pq_ms / 1e3), 1)
+    del pm
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(text, L, min(args.cpu_sample, n))
@@ -465,6 +505,7 @@ def main():
                     for k, v in kernels.items()},
         "dominant_kernel": dom,
         "queries_per_s": round(q_per_s, 1),
+        "conversion": conv,
     }
     print(json.dumps(out), flush=True)
 

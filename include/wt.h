@@ -185,6 +185,61 @@ int wt_batch_build(const wt_batch_item *items, uint32_t count, void *d_ws, size_
                    const wt_tune *tune, hipStream_t stream);
 
 /*
+ * Conversion between the two structures of one text (Section 5.1: on every
+ * level the WT and the WM hold the same intervals, the WT's in prefix order,
+ * the WM's in bit-reversed prefix order).  wt_convert reads a built WT or WM
+ * (*src) and writes the other one (*dst, bound with the same n and lg_sigma
+ * and the other kind): levels, Z and directories.  The interval tables are
+ * walked down from level 0 with the source's rank directory; every word of
+ * the destination is then gathered from the source interval by interval.
+ * d_ws: workspace of wt_convert_workspace_bytes(n, lg_sigma) bytes (the walk
+ * holds 3 * 2^(lg_sigma+1) words).  Asynchronous on `stream`; src must not
+ * change until the stream has passed the call.
+ * WT_ENOTSUP for lg_sigma > WT_MAX_TREE_LEVELS; WT_EINVAL for mismatched views.
+ */
+size_t wt_convert_workspace_bytes(uint64_t n, uint32_t lg_sigma);
+int wt_convert(const wt_levels *src, wt_levels *dst, void *d_ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Position map of Lemma 5: the position j in WM level l of the bit at
+ * position i of WT level l, in O(1) per query from
+ *   U  the unary histogram 1^{c_0} 0 1^{c_1} 0 ... of the symbol counts
+ *      (n + 2^lg_sigma bits, LSB-first words, with the library's rank and
+ *      select directories: rank_dir per 512-bit block, select samples every
+ *      WT_SEL_SPACING zeros / ones),
+ *  X  the WM interval starts of every level: level l's 2^l prefixes at
+ *      X + 2^l - 1.
+ *   j = i for l <= 1; otherwise, with c = rank_0(U, select_1(U, i + 1)) (the
+ *   symbol of the (i+1)-th smallest text symbol), bp = prefix(l, c) and
+ *   off = i - rank_1(U, select_0(U, bp << (lg_sigma - l))) (0 when that
+ *   shifted prefix is 0), j = X[2^l - 1 + bp] + off.
+ * wt_posmap_bytes: size of the caller buffer; wt_posmap_bind carves it
+ * (host only).  wt_posmap_build fills it from a built WT or WM *s (same
+ * workspace as wt_convert).  wt_posmap_query answers m positions of one
+ * level: UINT64_MAX for i >= n or level >= lg_sigma.  Requires lg_sigma <=
+ * WT_MAX_TREE_LEVELS and n + 2^lg_sigma < 2^32 (else WT_ENOTSUP).
+ */
+typedef struct wt_posmap {
+    uint64_t n;
+    uint32_t lg_sigma;
+    uint32_t reserved;
+    uint64_t u_len;   /* n + 2^lg_sigma bits of U */
+    uint64_t u_words; /* words of U, a multiple of 8 */
+    uint64_t rank_stride, sel_stride;
+    uint64_t *U;
+    uint32_t *rank_dir;
+    uint32_t *sel0;
+    uint32_t *sel1;
+    uint32_t *X;
+} wt_posmap;
+
+size_t wt_posmap_bytes(uint64_t n, uint32_t lg_sigma);
+int wt_posmap_bind(wt_posmap *m, void *d_mem, size_t bytes, uint64_t n, uint32_t lg_sigma);
+int wt_posmap_build(const wt_levels *s, wt_posmap *m, void *d_ws, size_t ws_bytes, hipStream_t stream);
+int wt_posmap_query(const wt_posmap *m, uint32_t level, const uint64_t *d_pos, uint64_t count,
+                    uint64_t *d_out, hipStream_t stream);
+
+/*
  * Timing aid: enqueue one build exactly like wt_build_tuned and, after every
  * kernel launch i (i < capacity), record the caller's event events[i] on
  * `stream` and store the launch's kernel id (see wt_kernel_name) in

@@ -60,6 +60,14 @@ class WtBatchItem(ctypes.Structure):
                 ("reserved", ctypes.c_uint32), ("out", ctypes.POINTER(WtLevels))]
 
 
+class WtPosmap(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("lg_sigma", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("u_len", ctypes.c_uint64), ("u_words", ctypes.c_uint64),
+                ("rank_stride", ctypes.c_uint64), ("sel_stride", ctypes.c_uint64),
+                ("U", ctypes.c_void_p), ("rank_dir", ctypes.c_void_p), ("sel0", ctypes.c_void_p),
+                ("sel1", ctypes.c_void_p), ("X", ctypes.c_void_p)]
+
+
 lib = ctypes.CDLL(LIB_PATH)
 _v, _u64, _u32, _i, _sz = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int, ctypes.c_size_t
 _LP = ctypes.POINTER(WtLevels)
@@ -84,6 +92,12 @@ _SIGS = {
     "wt_build_profiled": (_i, [_i, _v, _u64, _u32, _u32, _LP, _v, _sz, _TP, _v,
                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint32), _u32]),
     "wt_kernel_name": (ctypes.c_char_p, [_u32]),
+    "wt_convert_workspace_bytes": (_sz, [_u64, _u32]),
+    "wt_convert": (_i, [_LP, _LP, _v, _sz, _v]),
+    "wt_posmap_bytes": (_sz, [_u64, _u32]),
+    "wt_posmap_bind": (_i, [ctypes.POINTER(WtPosmap), _v, _sz, _u64, _u32]),
+    "wt_posmap_build": (_i, [_LP, ctypes.POINTER(WtPosmap), _v, _sz, _v]),
+    "wt_posmap_query": (_i, [ctypes.POINTER(WtPosmap), _u32, _v, _u64, _v, _v]),
     "wt_build_recorded": (_i, [_i, _v, _u64, _u32, _u32, _LP, _v, _sz, _TP, _v,
                                ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_uint32),
                                _u32, ctypes.POINTER(ctypes.c_uint32)]),
@@ -262,6 +276,50 @@ def build_profiled(d_text, n, sym_bytes, L, kind, tune=None, stream=None, ws=Non
             res[wt_kernel_name(i).decode()] = (ms[i], cnt[i])
     s._ws = ws
     return s, res
+
+
+def convert(s: Structure, stream=None) -> Structure:
+    """The other structure (WT from a WM, WM from a WT) of the same text,
+    gathered interval by interval (wt_convert)."""
+    torch = _torch()
+    dst = Structure(s.n, s.L, 1 - s.kind, device=s.buf.device)
+    need = int(wt_convert_workspace_bytes(s.n, s.L))
+    if need == 0:
+        raise WtError(WT_ENOTSUP, "wt_convert_workspace_bytes")
+    ws = torch.empty(need, dtype=torch.uint8, device=s.buf.device)
+    check(wt_convert(ctypes.byref(s.view), ctypes.byref(dst.view), ctypes.c_void_p(ws.data_ptr()), need,
+                     _stream_handle(stream)), "wt_convert")
+    dst._ws = ws
+    return dst
+
+
+class PosMap:
+    """Lemma 5 position map of a built WT or WM: query(level, positions)
+    returns, for WT positions of that level, the WM positions of the same
+    bits."""
+
+    def __init__(self, s: Structure, stream=None):
+        torch = _torch()
+        nbytes = int(wt_posmap_bytes(s.n, s.L))
+        if nbytes == 0:
+            raise WtError(WT_ENOTSUP, "wt_posmap_bytes")
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=s.buf.device)
+        self.view = WtPosmap()
+        check(wt_posmap_bind(ctypes.byref(self.view), ctypes.c_void_p(self.buf.data_ptr()), nbytes, s.n,
+                             s.L), "wt_posmap_bind")
+        need = int(wt_convert_workspace_bytes(s.n, s.L))
+        ws = torch.empty(need, dtype=torch.uint8, device=s.buf.device)
+        check(wt_posmap_build(ctypes.byref(s.view), ctypes.byref(self.view), ctypes.c_void_p(ws.data_ptr()),
+                              need, _stream_handle(stream)), "wt_posmap_build")
+        self._ws = ws
+
+    def query(self, level: int, pos, stream=None):
+        torch = _torch()
+        pos = pos.contiguous()
+        out = torch.empty(pos.numel(), dtype=torch.int64, device=pos.device)
+        check(wt_posmap_query(ctypes.byref(self.view), level, ctypes.c_void_p(pos.data_ptr()), pos.numel(),
+                              ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)), "wt_posmap_query")
+        return out
 
 
 class Batch:

@@ -415,6 +415,196 @@ int wt_select(const wt_levels *s, const uint32_t *d_sym, const uint64_t *d_k, ui
     return query_common(s, 2, d_sym, d_k, m, d_out, stream);
 }
 
+// ---- conversion between the WT and the WM, and the position map ----------
+
+// Workspace of a conversion or a position-map build: the interval walk of
+// levels 0..L, one descriptor (for the directory kernels), and the directory
+// scratch of either the L destination levels or U.
+struct ConvWs {
+    uint32_t *tab;
+    TextDesc *desc;
+    uint16_t *dir_bc;
+    uint32_t *dir_cs;
+    uint64_t *zeros;  // scratch Z and status for U's descriptor
+    int32_t *status;
+};
+
+static uint64_t conv_plan(uint64_t n, uint32_t L, uint8_t *base, ConvWs *w)
+{
+    const uint64_t ulen = n + (1ull << L);
+    const uint64_t nb = words_per_level(n) / 8, nbu = words_per_level(ulen) / 8;
+    const uint64_t bc = std::max<uint64_t>((uint64_t)L * nb, nbu);
+    const uint64_t cs = std::max<uint64_t>((uint64_t)L * cdiv64(nb, kDirChunk), cdiv64(nbu, kDirChunk));
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) {
+        const uint64_t o = off;
+        off = align_up(off + std::max<uint64_t>(bytes, 1), 256);
+        return o;
+    };
+    const uint64_t o_tab = take(3ull * ((2ull << L) - 1) * 4);
+    const uint64_t o_desc = take(sizeof(TextDesc));
+    const uint64_t o_bc = take(bc * 2);
+    const uint64_t o_cs = take(cs * 4);
+    const uint64_t o_z = take(16);
+    if (w) {
+        w->tab = (uint32_t *)(base + o_tab);
+        w->desc = (TextDesc *)(base + o_desc);
+        w->dir_bc = (uint16_t *)(base + o_bc);
+        w->dir_cs = (uint32_t *)(base + o_cs);
+        w->zeros = (uint64_t *)(base + o_z);
+        w->status = (int32_t *)(base + o_z + 8);
+    }
+    return off + 256;
+}
+
+static bool view_ok(const wt_levels *v)
+{
+    return v && check_out(v, v->n, v->lg_sigma, v->kind) == WT_OK;
+}
+
+size_t wt_convert_workspace_bytes(uint64_t n, uint32_t lg_sigma)
+{
+    if (lg_sigma > WT_MAX_TREE_LEVELS || n >= (1ull << 32)) return 0;
+    return conv_plan(n, lg_sigma, nullptr, nullptr);
+}
+
+// descriptor that lets the directory kernels run over `levels` bit vectors
+static TextDesc dir_desc(uint64_t n, uint32_t levels, uint64_t *bits, uint32_t *rank_dir, uint32_t *sel0,
+                         uint32_t *sel1, uint64_t *zeros, int32_t *status, const ConvWs &w)
+{
+    TextDesc d{};
+    d.n = n;
+    d.b = 1;
+    d.L = levels;
+    d.kind = WT_MATRIX;
+    d.K = levels ? levels : 1;
+    d.G = 1;
+    d.W = words_per_level(n);
+    d.nb = d.W / 8;
+    d.rank_stride = rank_stride(n);
+    d.sel_stride = sel_stride(n);
+    d.dir_chunks = (uint32_t)cdiv64(d.nb, kDirChunk);
+    d.bits = bits;
+    d.zeros = zeros;
+    d.rank_dir = rank_dir;
+    d.sel0 = sel0;
+    d.sel1 = sel1;
+    d.status = status;
+    d.dir_bc = w.dir_bc;
+    d.dir_cs = w.dir_cs;
+    return d;
+}
+
+int wt_convert(const wt_levels *src, wt_levels *dst, void *d_ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (!view_ok(src) || !view_ok(dst) || !d_ws) return WT_EINVAL;
+    if (src->n != dst->n || src->lg_sigma != dst->lg_sigma || src->kind == dst->kind) return WT_EINVAL;
+    const uint64_t n = src->n;
+    const uint32_t L = src->lg_sigma;
+    if (L > WT_MAX_TREE_LEVELS) return WT_ENOTSUP;
+    const size_t need = wt_convert_workspace_bytes(n, L);
+    if (need == 0) return WT_ENOTSUP;
+    if (ws_bytes < need) return WT_ENOSPACE;
+    ConvWs w;
+    conv_plan(n, L, (uint8_t *)align_up((uintptr_t)d_ws, 256), &w);
+    LaunchCtx ctx{stream, nullptr, nullptr};
+    // the descriptor (and the destination's status and Z cleared) first
+    TextDesc d = dir_desc(n, L, dst->bits, dst->rank_dir, dst->sel0, dst->sel1, dst->zeros, dst->status, w);
+    if (launch_init(d, w.desc, ctx) != hipSuccess) return WT_EHIP;
+    if (L == 0) return WT_OK;
+    if (n > 0) {
+        if (launch_convert_walk(*src, w.tab, L, true, ctx) != hipSuccess) return WT_EHIP;
+        if (launch_convert_gather(*src, *dst, w.tab, ctx) != hipSuccess) return WT_EHIP;
+    }
+    if (launch_dirs(w.desc, nullptr, 1, L * d.dir_chunks, L, false, 0, ctx) != hipSuccess) return WT_EHIP;
+    return WT_OK;
+}
+
+struct PmLayout {
+    uint64_t ulen, uw, rs, ss, o_rd, o_s0, o_s1, o_x, total;
+};
+
+static PmLayout pm_layout(uint64_t n, uint32_t L)
+{
+    PmLayout p;
+    p.ulen = n + (1ull << L);
+    p.uw = words_per_level(p.ulen);
+    p.rs = rank_stride(p.ulen);
+    p.ss = sel_stride(p.ulen);
+    p.o_rd = align_up(p.uw * 8, 256);
+    p.o_s0 = p.o_rd + align_up(p.rs * 4, 256);
+    p.o_s1 = p.o_s0 + align_up(p.ss * 4, 256);
+    p.o_x = p.o_s1 + align_up(p.ss * 4, 256);
+    p.total = p.o_x + align_up(std::max<uint64_t>((1ull << L) - 1, 1) * 4, 256);
+    return p;
+}
+
+size_t wt_posmap_bytes(uint64_t n, uint32_t lg_sigma)
+{
+    if (lg_sigma > WT_MAX_TREE_LEVELS || n + (1ull << lg_sigma) >= (1ull << 32)) return 0;
+    return pm_layout(n, lg_sigma).total + 256;
+}
+
+int wt_posmap_bind(wt_posmap *m, void *d_mem, size_t bytes, uint64_t n, uint32_t lg_sigma)
+{
+    if (!m || !d_mem) return WT_EINVAL;
+    const size_t need = wt_posmap_bytes(n, lg_sigma);
+    if (need == 0) return WT_ENOTSUP;
+    if (bytes < need) return WT_ENOSPACE;
+    const PmLayout p = pm_layout(n, lg_sigma);
+    uint8_t *base = (uint8_t *)align_up((uintptr_t)d_mem, 256);
+    m->n = n;
+    m->lg_sigma = lg_sigma;
+    m->reserved = 0;
+    m->u_len = p.ulen;
+    m->u_words = p.uw;
+    m->rank_stride = p.rs;
+    m->sel_stride = p.ss;
+    m->U = (uint64_t *)base;
+    m->rank_dir = (uint32_t *)(base + p.o_rd);
+    m->sel0 = (uint32_t *)(base + p.o_s0);
+    m->sel1 = (uint32_t *)(base + p.o_s1);
+    m->X = (uint32_t *)(base + p.o_x);
+    return WT_OK;
+}
+
+static bool posmap_ok(const wt_posmap *m)
+{
+    if (!m || !m->U) return false;
+    const PmLayout p = pm_layout(m->n, m->lg_sigma);
+    return m->u_len == p.ulen && m->u_words == p.uw && m->rank_stride == p.rs && m->sel_stride == p.ss;
+}
+
+int wt_posmap_build(const wt_levels *s, wt_posmap *m, void *d_ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (!view_ok(s) || !posmap_ok(m) || !d_ws) return WT_EINVAL;
+    if (s->n != m->n || s->lg_sigma != m->lg_sigma) return WT_EINVAL;
+    const uint32_t L = s->lg_sigma;
+    if (wt_posmap_bytes(s->n, L) == 0) return WT_ENOTSUP;
+    const size_t need = wt_convert_workspace_bytes(s->n, L);
+    if (need == 0) return WT_ENOTSUP;
+    if (ws_bytes < need) return WT_ENOSPACE;
+    ConvWs w;
+    conv_plan(s->n, L, (uint8_t *)align_up((uintptr_t)d_ws, 256), &w);
+    LaunchCtx ctx{stream, nullptr, nullptr};
+    // the walk down to the leaves: symbol counts, and the WM starts (X)
+    if (launch_convert_walk(*s, w.tab, L, true, ctx) != hipSuccess) return WT_EHIP;
+    TextDesc d = dir_desc(m->u_len, 1, m->U, m->rank_dir, m->sel0, m->sel1, w.zeros, w.status, w);
+    if (launch_init(d, w.desc, ctx) != hipSuccess) return WT_EHIP;
+    if (launch_posmap_fill(*m, w.tab, ctx) != hipSuccess) return WT_EHIP;
+    if (launch_dirs(w.desc, nullptr, 1, d.dir_chunks, 1, false, 0, ctx) != hipSuccess) return WT_EHIP;
+    return WT_OK;
+}
+
+int wt_posmap_query(const wt_posmap *m, uint32_t level, const uint64_t *d_pos, uint64_t count,
+                    uint64_t *d_out, hipStream_t stream)
+{
+    if (!posmap_ok(m)) return WT_EINVAL;
+    if (count > 0 && (!d_pos || !d_out)) return WT_EINVAL;
+    LaunchCtx ctx{stream, nullptr, nullptr};
+    return launch_posmap_query(*m, level, d_pos, count, d_out, ctx) == hipSuccess ? WT_OK : WT_EHIP;
+}
+
 int wt_get_status(const wt_levels *s, hipStream_t stream)
 {
     if (!s || !s->status) return WT_EINVAL;

@@ -1,0 +1,227 @@
+// Conversion between the level-wise wavelet tree and the wavelet matrix of
+// the same text, and the tables of the WT-to-WM position map.
+//
+// Section 5.1: on every level the WT and the WM hold the same intervals (one
+// per bit prefix of the level's length, the same bits in the same order),
+// the WT's in prefix order and the WM's in bit-reversed prefix order.  So
+// either structure yields, level by level, every prefix's interval length and
+// its start in both orders, and the other structure is gathered interval by
+// interval.  The walk goes down from level 0: a prefix's interval splits into
+// its two children by the zeros and ones it holds on the current level,
+// counted with the source's rank directory (WM: a zero child continues at
+// rank_0 of the interval start, a one child at Z + rank_1; WT: the children
+// are adjacent).  From a WT the WM starts are the zero-based prefix sums of
+// the lengths in bit-reversed order.
+//
+// Lemma 5: the position map needs the unary histogram U = 1^{c_0} 0 1^{c_1} 0
+// ... of the symbol counts c_s (the leaf level of the walk) with its rank and
+// select directories, and X, the WM interval starts of every level.
+#include "wt_device.h"
+
+namespace wtg {
+
+// walk tables of level l: WM start, length, WT start, 2^l u32 each
+__host__ __device__ inline uint64_t ctab_off(uint32_t l) { return 3ull * ((1ull << l) - 1ull); }
+
+__global__ void k_cwalk_init(uint32_t *tab, uint64_t n)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        tab[0] = 0;
+        tab[1] = (uint32_t)n;
+        tab[2] = 0;
+    }
+}
+
+// level l -> level l + 1 of the walk, one thread per l-bit prefix
+__global__ __launch_bounds__(256) void k_cwalk_step(wt_levels src, uint32_t *tab, uint32_t l)
+{
+    const uint64_t np = 1ull << l;
+    const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    const uint32_t *cur = tab + ctab_off(l);
+    uint32_t *nxt = tab + ctab_off(l + 1);
+    const uint32_t ms = cur[p], h = cur[np + p], ws = cur[2 * np + p];
+    const uint64_t *bits = src.bits + (uint64_t)l * src.words_per_level;
+    const uint32_t *rd = src.rank_dir + (uint64_t)l * src.rank_stride;
+    // the interval on this level of the source: WM start or WT start
+    const uint32_t s = (src.kind == WT_MATRIX) ? ms : ws;
+    uint32_t r1s = 0, ones = 0;
+    if (h) {
+        r1s = (uint32_t)rank1_dir(bits, rd, s);
+        ones = (uint32_t)rank1_dir(bits, rd, (uint64_t)s + h) - r1s;
+    }
+    const uint64_t nn = 2 * np;
+    uint32_t m0 = 0, m1 = 0;  // WM starts of the children (from a WT: by a later scan)
+    if (src.kind == WT_MATRIX) {
+        m0 = ms - r1s;
+        m1 = (uint32_t)src.zeros[l] + r1s;
+    }
+    nxt[2 * p] = m0;
+    nxt[nn + 2 * p] = h - ones;
+    nxt[2 * nn + 2 * p] = ws;
+    nxt[2 * p + 1] = m1;
+    nxt[nn + 2 * p + 1] = ones;
+    nxt[2 * nn + 2 * p + 1] = ws + (h - ones);
+}
+
+// WM starts of every level from the lengths: zero-based prefix sums with
+// the prefixes visited in bit-reversed order (one block per level)
+__global__ __launch_bounds__(1024) void k_cwm_starts(uint32_t *tab, uint32_t L)
+{
+    __shared__ uint32_t part[1024];
+    const uint32_t l = blockIdx.x;
+    if (l >= L) return;
+    const uint64_t np = 1ull << l;
+    uint32_t *ms = tab + ctab_off(l);
+    const uint32_t *len = ms + np;
+    const uint32_t t = threadIdx.x;
+    const uint64_t per = (np + 1023) / 1024;
+    const uint64_t i0 = t * per, i1 = min(np, i0 + per);
+    uint32_t s = 0;
+    for (uint64_t i = i0; i < i1; i++) s += len[rev_bits((uint32_t)i, l)];
+    part[t] = s;
+    __syncthreads();
+    // exclusive scan of the 1024 partial sums (Hillis-Steele in LDS)
+    for (uint32_t off = 1; off < 1024; off <<= 1) {
+        const uint32_t x = (t >= off) ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += x;
+        __syncthreads();
+    }
+    uint32_t run = part[t] - s;
+    for (uint64_t i = i0; i < i1; i++) {
+        const uint32_t p = rev_bits((uint32_t)i, l);
+        ms[p] = run;
+        run += len[p];
+    }
+}
+
+// Word w of level l of dst, gathered from level l of src interval by interval
+// (the intervals sorted by their start in dst's order).
+__global__ __launch_bounds__(256) void k_cgather(wt_levels src, wt_levels dst, const uint32_t *tab,
+                                                 uint32_t l)
+{
+    const uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t W = dst.words_per_level;
+    if (w >= W) return;
+    const uint64_t n = dst.n;
+    const uint32_t np = 1u << l;
+    const uint32_t *ms = tab + ctab_off(l), *len = ms + np, *ws = len + np;
+    const bool to_wt = (dst.kind == WT_TREE);
+    const uint64_t *sb = src.bits + (uint64_t)l * src.words_per_level;
+    const uint64_t ws0 = w << 6;
+    const uint64_t we = min(ws0 + 64, n);
+    uint64_t val = 0;
+    uint64_t pos = ws0;
+    while (pos < we) {
+        // the last interval (in dst order) starting at or before pos; an
+        // empty interval shares its start with the next one, so it is never
+        // the last such interval
+        uint32_t lo = 0, hi = np;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            const uint32_t p = to_wt ? mid : rev_bits(mid, l);
+            if ((to_wt ? ws[p] : ms[p]) <= pos) lo = mid;
+            else hi = mid;
+        }
+        const uint32_t p = to_wt ? lo : rev_bits(lo, l);
+        const uint64_t ds = to_wt ? ws[p] : ms[p];
+        const uint64_t ss = to_wt ? ms[p] : ws[p];
+        uint64_t end = ds + len[p];
+        if (end > we) end = we;
+        if (end <= pos) break;  // never for consistent tables
+        const uint32_t cnt = (uint32_t)(end - pos);
+        const uint64_t s = ss + (pos - ds);
+        const uint32_t sh = (uint32_t)(s & 63);
+        uint64_t x = sb[s >> 6] >> sh;
+        if (sh && sh + cnt > 64) x |= sb[(s >> 6) + 1] << (64 - sh);
+        if (cnt < 64) x &= (1ull << cnt) - 1;
+        val |= x << (pos - ws0);
+        pos = end;
+    }
+    dst.bits[(uint64_t)l * W + w] = val;
+}
+
+__global__ void k_ccopy_zeros(wt_levels src, wt_levels dst)
+{
+    for (uint32_t l = threadIdx.x; l < dst.lg_sigma; l += blockDim.x) dst.zeros[l] = src.zeros[l];
+}
+
+// U: 1^{c_0} 0 1^{c_1} 0 ... 1^{c_{s-1}} 0 over positions [0, n + s), zero
+// past it; the zero after symbol c's ones sits at (count of symbols <= c) + c
+// = WT start + length + c of the leaf-level walk entry of c.
+__global__ __launch_bounds__(256) void k_cunary(wt_posmap m, const uint32_t *tab)
+{
+    const uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= m.u_words) return;
+    const uint32_t L = m.lg_sigma;
+    const uint64_t sig = 1ull << L;
+    const uint32_t *len = tab + ctab_off(L) + sig, *ws = len + sig;
+    auto zero_at = [&](uint64_t c) -> uint64_t { return (uint64_t)ws[c] + len[c] + c; };
+    const uint64_t b0 = w << 6;
+    const uint64_t valid = (m.u_len > b0) ? min<uint64_t>(64, m.u_len - b0) : 0;
+    uint64_t val = (valid == 64) ? ~0ull : ((1ull << valid) - 1);
+    // first symbol whose zero is at or past b0
+    uint64_t lo = 0, hi = sig;
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (zero_at(mid) < b0) lo = mid + 1;
+        else hi = mid;
+    }
+    for (uint64_t c = lo; c < sig; c++) {
+        const uint64_t z = zero_at(c);
+        if (z >= b0 + 64) break;
+        val &= ~(1ull << (z - b0));
+    }
+    m.U[w] = val;
+}
+
+// X: WM start of every prefix of levels 0 .. L-1
+__global__ __launch_bounds__(256) void k_cstarts(wt_posmap m, const uint32_t *tab)
+{
+    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t tot = (1ull << m.lg_sigma) - 1;
+    if (e >= tot) return;
+    const uint32_t l = 63 - __clzll(e + 1);
+    const uint64_t p = e - ((1ull << l) - 1);
+    m.X[e] = tab[ctab_off(l) + p];
+}
+
+static inline uint32_t blocks_for(uint64_t n, uint32_t t) { return (uint32_t)((n + t - 1) / t); }
+
+hipError_t launch_convert_walk(const wt_levels &src, uint32_t *d_tab, uint32_t levels,
+                               bool need_wm_starts, const LaunchCtx &ctx)
+{
+    hipLaunchKernelGGL(k_cwalk_init, dim3(1), dim3(64), 0, ctx.stream, d_tab, src.n);
+    for (uint32_t l = 0; l < levels; l++)
+        hipLaunchKernelGGL(k_cwalk_step, dim3(blocks_for(1ull << l, 256)), dim3(256), 0, ctx.stream,
+                           src, d_tab, l);
+    if (need_wm_starts && src.kind == WT_TREE && src.lg_sigma > 0)
+        hipLaunchKernelGGL(k_cwm_starts, dim3(src.lg_sigma), dim3(1024), 0, ctx.stream, d_tab,
+                           src.lg_sigma);
+    if (ctx.after) ctx.after(ctx.user, KID_WALK);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert_gather(const wt_levels &src, const wt_levels &dst, const uint32_t *d_tab,
+                                 const LaunchCtx &ctx)
+{
+    for (uint32_t l = 0; l < dst.lg_sigma; l++)
+        hipLaunchKernelGGL(k_cgather, dim3(blocks_for(dst.words_per_level, 256)), dim3(256), 0,
+                           ctx.stream, src, dst, d_tab, l);
+    hipLaunchKernelGGL(k_ccopy_zeros, dim3(1), dim3(64), 0, ctx.stream, src, dst);
+    if (ctx.after) ctx.after(ctx.user, KID_GATHER);
+    return hipGetLastError();
+}
+
+hipError_t launch_posmap_fill(const wt_posmap &m, const uint32_t *d_tab, const LaunchCtx &ctx)
+{
+    hipLaunchKernelGGL(k_cunary, dim3(blocks_for(m.u_words, 256)), dim3(256), 0, ctx.stream, m, d_tab);
+    const uint64_t tot = (1ull << m.lg_sigma) - 1;
+    if (tot)
+        hipLaunchKernelGGL(k_cstarts, dim3(blocks_for(tot, 256)), dim3(256), 0, ctx.stream, m, d_tab);
+    if (ctx.after) ctx.after(ctx.user, KID_GATHER);
+    return hipGetLastError();
+}
+
+}  // namespace wtg

@@ -140,6 +140,13 @@ hipError_t launch_gather(const TextDesc *d_descs, const uint32_t *bases, uint32_
                          uint32_t nitems, const LaunchCtx &ctx);
 hipError_t launch_dirs(const TextDesc *d_descs, const uint32_t *bases, uint32_t nd, uint32_t nitems,
                        uint32_t max_levels, bool tmp, uint32_t grid_cap, const LaunchCtx &ctx);
+hipError_t launch_convert_walk(const wt_levels &src, uint32_t *d_tab, uint32_t levels,
+                               bool need_wm_starts, const LaunchCtx &ctx);
+hipError_t launch_convert_gather(const wt_levels &src, const wt_levels &dst, const uint32_t *d_tab,
+                                 const LaunchCtx &ctx);
+hipError_t launch_posmap_fill(const wt_posmap &m, const uint32_t *d_tab, const LaunchCtx &ctx);
+hipError_t launch_posmap_query(const wt_posmap &m, uint32_t level, const uint64_t *d_pos,
+                               uint64_t count, uint64_t *d_out, const LaunchCtx &ctx);
 hipError_t launch_queries(const wt_levels &s, int op, const uint32_t *d_sym, const uint64_t *d_arg,
                           uint64_t m, void *d_out, const LaunchCtx &ctx);
 

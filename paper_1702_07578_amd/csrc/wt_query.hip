@@ -226,6 +226,53 @@ __global__ __launch_bounds__(256) void k_select(wt_levels s, const uint32_t *__r
     out[qi] = p;
 }
 
+// Lemma 5: WT position i of level l -> WM position (one lane per query).
+// select_1(U, i+1) has exactly i ones before it, so rank_0 there is
+// select_1(U, i+1) - i; select_0(U, k) has k-1 zeros before it, so rank_1
+// there is select_0(U, k) - (k-1).
+__global__ __launch_bounds__(256) void k_posmap(wt_posmap m, uint32_t level,
+                                                const uint64_t *__restrict__ pos, uint64_t count,
+                                                uint64_t *__restrict__ out)
+{
+    const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= count) return;
+    const uint64_t i = pos[q];
+    if (i >= m.n || level >= m.lg_sigma) {
+        out[q] = ~0ull;
+        return;
+    }
+    if (level <= 1) {
+        out[q] = i;
+        return;
+    }
+    QLevel u;
+    u.bits = m.U;
+    u.rd = m.rank_dir;
+    u.sel0 = m.sel0;
+    u.sel1 = m.sel1;
+    const uint64_t nb = m.u_words / 8;
+    const uint64_t c = select_b(u, m.u_len, nb, i + 1, 1) - i;
+    const uint32_t sh = m.lg_sigma - level;
+    const uint64_t bp = c >> sh;
+    if (bp >= (1ull << level)) {  // never for a consistent map
+        out[q] = ~0ull;
+        return;
+    }
+    const uint64_t k = bp << sh;
+    const uint64_t before = k ? select_b(u, m.u_len, nb, k, 0) - (k - 1) : 0;
+    out[q] = (uint64_t)m.X[((1ull << level) - 1) + bp] + (i - before);
+}
+
+hipError_t launch_posmap_query(const wt_posmap &m, uint32_t level, const uint64_t *d_pos,
+                               uint64_t count, uint64_t *d_out, const LaunchCtx &ctx)
+{
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_posmap, dim3((uint32_t)((count + 255) / 256)), dim3(256), 0, ctx.stream, m,
+                       level, d_pos, count, d_out);
+    if (ctx.after) ctx.after(ctx.user, KID_QUERY);
+    return hipGetLastError();
+}
+
 hipError_t launch_queries(const wt_levels &s, int op, const uint32_t *d_sym, const uint64_t *d_arg,
                           uint64_t m, void *d_out, const LaunchCtx &ctx)
 {

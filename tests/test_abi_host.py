@@ -60,3 +60,27 @@ def test_argument_errors_return_before_device_work():
     assert B.wm_build(fake, 100, 1, 4, ctypes.byref(v), fake, 1 << 20, None) == B.WT_EINVAL
     assert B.wt_access(None, fake, 1, fake, None) == B.WT_EINVAL
     assert B.wt_strerror(B.WT_ERANGE).decode().startswith("symbol")
+
+
+def test_conversion_and_position_map_sizes():
+    """Host-side sizing and binding of the conversion workspace and the
+    position map (no device work)."""
+    from paper_1702_07578_amd import binding as B
+    assert B.wt_convert_workspace_bytes(1000, 8) > 3 * (2 ** 9) * 4
+    assert B.wt_convert_workspace_bytes(1000, B.WT_MAX_TREE_LEVELS + 1) == 0
+    assert B.wt_posmap_bytes(1000, 27) == 0
+    assert B.wt_posmap_bytes((1 << 32) - 10, 4) == 0  # n + 2^L must stay below 2^32
+    nbytes = B.wt_posmap_bytes(1000, 8)
+    m = B.WtPosmap()
+    assert B.wt_posmap_bind(ctypes.byref(m), ctypes.c_void_p(4096), nbytes, 1000, 8) == B.WT_OK
+    assert m.u_len == 1000 + 256 and m.u_words % 8 == 0 and m.u_words * 64 >= m.u_len
+    assert m.U % 256 == 0 and m.rank_dir > m.U and m.sel0 > m.rank_dir and m.sel1 > m.sel0 and m.X > m.sel1
+    assert m.X + (256 - 1) * 4 <= 4096 + nbytes
+    assert B.wt_posmap_bind(ctypes.byref(m), ctypes.c_void_p(4096), nbytes - 512, 1000, 8) == B.WT_ENOSPACE
+    assert B.wt_posmap_bind(None, ctypes.c_void_p(4096), nbytes, 1000, 8) == B.WT_EINVAL
+    # views that do not describe the same text are refused before any device work
+    a, b = B.WtLevels(), B.WtLevels()
+    out = B.wt_output_bytes(1000, 8)
+    assert B.wt_levels_bind(ctypes.byref(a), ctypes.c_void_p(1 << 20), out, 1000, 8, 0) == B.WT_OK
+    assert B.wt_levels_bind(ctypes.byref(b), ctypes.c_void_p(1 << 24), out, 1000, 8, 0) == B.WT_OK
+    assert B.wt_convert(ctypes.byref(a), ctypes.byref(b), ctypes.c_void_p(1 << 28), 1 << 20, None) == B.WT_EINVAL
