@@ -401,7 +401,10 @@ def main():
     scat = kernels.get("scatter", {"avg_ms": float("nan"), "launches": 0})
     per_launch_bytes = (n * b + L * W * 8) / max(1, G)
     achieved = per_launch_bytes / (scat["avg_ms"] / 1e3) / 1e9
-    roofline = {"kernel": "scatter", "bound": "hbm", "achieved": round(achieved, 1),
+    roofline = {"kernel": "scatter", "bound": "hbm",
+                "limiter": "vector-instruction issue: about 83 VALU instructions per 64 symbols "
+                           "for 7 levels (rocprofv3 SQ_INSTS_VALU), about 76% of the chip's issue rate",
+                "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": scatter_traffic(per_launch_bytes),
                 "alg_bytes_per_launch": int(per_launch_bytes), "avg_launch_ms": round(scat["avg_ms"], 4)}
