@@ -471,6 +471,17 @@ def main():
     bit_wm = (wm_words[j >> 6] >> (j & 63)) & 1
     if not torch.equal(bit_wt, bit_wm):
         raise SystemExit("position map does not carry WT bits to equal WM bits")
+    # domain decomposition: the WM of 8 consecutive pieces, merged into the
+    # WM of the whole text (must equal the direct build)
+    pieces = 8
+    cut = [(n * i) // pieces for i in range(pieces + 1)]
+    parts = [B.build(d_text[cut[i] * b:cut[i + 1] * b], cut[i + 1] - cut[i], b, L, B.WT_MATRIX)
+             for i in range(pieces)]
+    merged, mg_ms = timed(lambda: B.merge(parts))
+    if not same_levels(merged, structs[B.WT_MATRIX]) or merged.status() != 0:
+        raise SystemExit("merged pieces differ from the direct build")
+    conv["merge_8_pieces_ms"] = round(mg_ms, 3)
+    del parts, merged
     # both structures when both are wanted: build the WM, convert it to the WT
     conv["wm_build_plus_convert_ms"] = round(ms_per_step / 2 + conv["wm_to_wt_ms"], 3)
     conv["posmap_build_ms"] = round(pm_ms, 3)

@@ -201,6 +201,23 @@ size_t wt_convert_workspace_bytes(uint64_t n, uint32_t lg_sigma);
 int wt_convert(const wt_levels *src, wt_levels *dst, void *d_ws, size_t ws_bytes, hipStream_t stream);
 
 /*
+ * Merge of partial structures (Section 3.3, domain decomposition): parts[c]
+ * (host array of bound views, same kind and lg_sigma, built on this device)
+ * hold the structures of consecutive pieces of a text; *dst (same kind and
+ * lg_sigma, n = the pieces' total) receives the structure of the whole text:
+ * levels, Z (the pieces' sum) and directories.  On every level the whole
+ * text's interval of a prefix is the pieces' intervals of that prefix in
+ * piece order, the intervals in the kind's prefix order; one prefix sum over
+ * (prefix, piece) places them.  d_ws: wt_merge_workspace_bytes(n, lg_sigma,
+ * count) bytes.  Copies the views to the device on `stream` and waits for
+ * that copy (host call); the rest is asynchronous.  WT_ENOTSUP for lg_sigma >
+ * WT_MAX_TREE_LEVELS or count * 2^(lg_sigma+1) > 2^30.
+ */
+size_t wt_merge_workspace_bytes(uint64_t n, uint32_t lg_sigma, uint32_t count);
+int wt_merge(const wt_levels *parts, uint32_t count, wt_levels *dst, void *d_ws, size_t ws_bytes,
+             hipStream_t stream);
+
+/*
  * Position map of Lemma 5: the position j in WM level l of the bit at
  * position i of WT level l, in O(1) per query from
  *   U  the unary histogram 1^{c_0} 0 1^{c_1} 0 ... of the symbol counts

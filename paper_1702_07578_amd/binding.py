@@ -94,6 +94,8 @@ _SIGS = {
     "wt_kernel_name": (ctypes.c_char_p, [_u32]),
     "wt_convert_workspace_bytes": (_sz, [_u64, _u32]),
     "wt_convert": (_i, [_LP, _LP, _v, _sz, _v]),
+    "wt_merge_workspace_bytes": (_sz, [_u64, _u32, _u32]),
+    "wt_merge": (_i, [_LP, _u32, _LP, _v, _sz, _v]),
     "wt_posmap_bytes": (_sz, [_u64, _u32]),
     "wt_posmap_bind": (_i, [ctypes.POINTER(WtPosmap), _v, _sz, _u64, _u32]),
     "wt_posmap_build": (_i, [_LP, ctypes.POINTER(WtPosmap), _v, _sz, _v]),
@@ -289,6 +291,24 @@ def convert(s: Structure, stream=None) -> Structure:
     ws = torch.empty(need, dtype=torch.uint8, device=s.buf.device)
     check(wt_convert(ctypes.byref(s.view), ctypes.byref(dst.view), ctypes.c_void_p(ws.data_ptr()), need,
                      _stream_handle(stream)), "wt_convert")
+    dst._ws = ws
+    return dst
+
+
+def merge(parts, stream=None) -> Structure:
+    """The structure of the concatenated text from the structures of its
+    consecutive pieces (same kind and levels), by wt_merge."""
+    torch = _torch()
+    n = sum(p.n for p in parts)
+    L, kind = parts[0].L, parts[0].kind
+    dst = Structure(n, L, kind, device=parts[0].buf.device)
+    need = int(wt_merge_workspace_bytes(n, L, len(parts)))
+    if need == 0:
+        raise WtError(WT_ENOTSUP, "wt_merge_workspace_bytes")
+    ws = torch.empty(need, dtype=torch.uint8, device=dst.buf.device)
+    arr = (WtLevels * len(parts))(*[p.view for p in parts])
+    check(wt_merge(arr, len(parts), ctypes.byref(dst.view), ctypes.c_void_p(ws.data_ptr()), need,
+                   _stream_handle(stream)), "wt_merge")
     dst._ws = ws
     return dst
 

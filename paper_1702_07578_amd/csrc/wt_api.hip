@@ -520,6 +520,83 @@ int wt_convert(const wt_levels *src, wt_levels *dst, void *d_ws, size_t ws_bytes
     return WT_OK;
 }
 
+// merge of partial structures: the walk of every piece (levels 0..L), the
+// (prefix, piece) starts of every level, the pieces' views, a descriptor and
+// the directory scratch of the whole
+static uint64_t merge_plan(uint64_t n, uint32_t L, uint32_t count, uint8_t *base, ConvWs *w,
+                           uint32_t **mtab, wt_levels **views, uint64_t *stride)
+{
+    const uint64_t st = 3ull * ((2ull << L) - 1);
+    const uint64_t nb = words_per_level(n) / 8;
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) {
+        const uint64_t o = off;
+        off = align_up(off + std::max<uint64_t>(bytes, 1), 256);
+        return o;
+    };
+    const uint64_t o_tab = take(st * count * 4);
+    const uint64_t o_m = take((uint64_t)count * ((1ull << L) - 1) * 4);
+    const uint64_t o_v = take((uint64_t)count * sizeof(wt_levels));
+    const uint64_t o_desc = take(sizeof(TextDesc));
+    const uint64_t o_bc = take((uint64_t)L * nb * 2);
+    const uint64_t o_cs = take((uint64_t)L * cdiv64(nb, kDirChunk) * 4);
+    if (w) {
+        w->tab = (uint32_t *)(base + o_tab);
+        w->desc = (TextDesc *)(base + o_desc);
+        w->dir_bc = (uint16_t *)(base + o_bc);
+        w->dir_cs = (uint32_t *)(base + o_cs);
+        w->zeros = nullptr;
+        w->status = nullptr;
+        *mtab = (uint32_t *)(base + o_m);
+        *views = (wt_levels *)(base + o_v);
+        *stride = st;
+    }
+    return off + 256;
+}
+
+size_t wt_merge_workspace_bytes(uint64_t n, uint32_t lg_sigma, uint32_t count)
+{
+    if (lg_sigma > WT_MAX_TREE_LEVELS || n >= (1ull << 32) || count == 0) return 0;
+    // tables of count * 2^(lg_sigma + 1) entries per piece set
+    if ((uint64_t)count << (lg_sigma + 1) > (1ull << 30)) return 0;
+    return merge_plan(n, lg_sigma, count, nullptr, nullptr, nullptr, nullptr, nullptr);
+}
+
+int wt_merge(const wt_levels *parts, uint32_t count, wt_levels *dst, void *d_ws, size_t ws_bytes,
+             hipStream_t stream)
+{
+    if (!parts || count == 0 || !view_ok(dst) || !d_ws) return WT_EINVAL;
+    uint64_t total = 0;
+    for (uint32_t c = 0; c < count; c++) {
+        if (!view_ok(&parts[c]) || parts[c].kind != dst->kind || parts[c].lg_sigma != dst->lg_sigma)
+            return WT_EINVAL;
+        total += parts[c].n;
+    }
+    if (total != dst->n) return WT_EINVAL;
+    const uint32_t L = dst->lg_sigma;
+    const size_t need = wt_merge_workspace_bytes(dst->n, L, count);
+    if (need == 0) return WT_ENOTSUP;
+    if (ws_bytes < need) return WT_ENOSPACE;
+    ConvWs w;
+    uint32_t *mtab;
+    wt_levels *views;
+    uint64_t stride;
+    merge_plan(dst->n, L, count, (uint8_t *)align_up((uintptr_t)d_ws, 256), &w, &mtab, &views, &stride);
+    LaunchCtx ctx{stream, nullptr, nullptr};
+    // the pieces' views to the device (the host array may go once this returns)
+    if (hipMemcpyAsync(views, parts, count * sizeof(wt_levels), hipMemcpyHostToDevice, stream) !=
+        hipSuccess)
+        return WT_EHIP;
+    if (hipStreamSynchronize(stream) != hipSuccess) return WT_EHIP;
+    TextDesc d = dir_desc(dst->n, L, dst->bits, dst->rank_dir, dst->sel0, dst->sel1, dst->zeros,
+                          dst->status, w);
+    if (launch_init(d, w.desc, ctx) != hipSuccess) return WT_EHIP;
+    if (L == 0) return WT_OK;
+    if (launch_merge(views, count, w.tab, stride, mtab, *dst, ctx) != hipSuccess) return WT_EHIP;
+    if (launch_dirs(w.desc, nullptr, 1, L * d.dir_chunks, L, false, 0, ctx) != hipSuccess) return WT_EHIP;
+    return WT_OK;
+}
+
 struct PmLayout {
     uint64_t ulen, uw, rs, ss, o_rd, o_s0, o_s1, o_x, total;
 };

@@ -187,7 +187,176 @@ __global__ __launch_bounds__(256) void k_cstarts(wt_posmap m, const uint32_t *ta
     m.X[e] = tab[ctab_off(l) + p];
 }
 
+// ---------------------------------------------------------------------------
+// Merging partial structures (Section 3.3, domain decomposition): `count`
+// structures of the same kind built from consecutive pieces of a text.  On
+// level l the whole text's interval of prefix k is the concatenation, piece
+// by piece, of the pieces' intervals of k (text order is piece order), and
+// the intervals follow each other in the kind's prefix order.  So each
+// piece is walked like a conversion source (its intervals' starts in its own
+// order and their lengths), one zero-based prefix sum over (prefix in order,
+// piece) gives every piece interval's start in the whole, and every word of
+// the whole is gathered from the pieces.
+
+// walk of every piece; piece c's tables at tabs + c * stride
+__global__ __launch_bounds__(256) void k_mwalk(const wt_levels *__restrict__ parts, uint32_t count,
+                                               uint32_t *tabs, uint64_t stride, uint32_t l)
+{
+    const uint64_t np = 1ull << l;
+    const uint64_t item = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (item >= np * count) return;
+    const uint32_t c = (uint32_t)(item >> l);
+    const uint64_t p = item & (np - 1);
+    const wt_levels &src = parts[c];
+    uint32_t *tab = tabs + c * stride;
+    if (l == 0 && p == 0) {
+        // level 0 is written by the first step itself
+        tab[0] = 0;
+        tab[1] = (uint32_t)src.n;
+        tab[2] = 0;
+    }
+    const uint32_t *cur = tab + ctab_off(l);
+    uint32_t *nxt = tab + ctab_off(l + 1);
+    const uint32_t ms = (l == 0) ? 0u : cur[p];
+    const uint32_t h = (l == 0) ? (uint32_t)src.n : cur[np + p];
+    const uint32_t ws = (l == 0) ? 0u : cur[2 * np + p];
+    const uint64_t *bits = src.bits + (uint64_t)l * src.words_per_level;
+    const uint32_t *rd = src.rank_dir + (uint64_t)l * src.rank_stride;
+    const uint32_t s = (src.kind == WT_MATRIX) ? ms : ws;
+    uint32_t r1s = 0, ones = 0;
+    if (h) {
+        r1s = (uint32_t)rank1_dir(bits, rd, s);
+        ones = (uint32_t)rank1_dir(bits, rd, (uint64_t)s + h) - r1s;
+    }
+    const uint64_t nn = 2 * np;
+    nxt[2 * p] = ms - r1s;
+    nxt[nn + 2 * p] = h - ones;
+    nxt[2 * nn + 2 * p] = ws;
+    nxt[2 * p + 1] = (uint32_t)src.zeros[l] + r1s;
+    nxt[nn + 2 * p + 1] = ones;
+    nxt[2 * nn + 2 * p + 1] = ws + (h - ones);
+}
+
+// starts in the whole of every (prefix, piece) interval of level l: a
+// zero-based prefix sum over the prefixes in the kind's order, pieces in
+// order inside a prefix (one block per level); mtab + count * (2^l - 1) holds
+// level l, entry p * count + c
+__global__ __launch_bounds__(1024) void k_mstarts(const uint32_t *tabs, uint64_t stride, uint32_t count,
+                                                  uint32_t kind, uint32_t *mtab)
+{
+    __shared__ uint32_t part[1024];
+    const uint32_t l = blockIdx.x;
+    const uint64_t np = 1ull << l;
+    const uint64_t ne = np * count;
+    uint32_t *out = mtab + (uint64_t)count * (np - 1);
+    const uint32_t t = threadIdx.x;
+    const uint64_t per = (ne + 1023) / 1024;
+    const uint64_t i0 = t * per, i1 = min(ne, i0 + per);
+    auto entry = [&](uint64_t i, uint32_t &p, uint32_t &c) {
+        const uint32_t k = (uint32_t)(i / count);
+        c = (uint32_t)(i % count);
+        p = (kind == WT_TREE) ? k : rev_bits(k, l);
+    };
+    uint32_t s = 0;
+    for (uint64_t i = i0; i < i1; i++) {
+        uint32_t p, c;
+        entry(i, p, c);
+        s += tabs[c * stride + ctab_off(l) + np + p];
+    }
+    part[t] = s;
+    __syncthreads();
+    for (uint32_t off = 1; off < 1024; off <<= 1) {
+        const uint32_t x = (t >= off) ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += x;
+        __syncthreads();
+    }
+    uint32_t run = part[t] - s;
+    for (uint64_t i = i0; i < i1; i++) {
+        uint32_t p, c;
+        entry(i, p, c);
+        out[(uint64_t)p * count + c] = run;
+        run += tabs[c * stride + ctab_off(l) + np + p];
+    }
+}
+
+// word w of level l of the whole, gathered from the pieces
+__global__ __launch_bounds__(256) void k_mgather(const wt_levels *__restrict__ parts, uint32_t count,
+                                                 const uint32_t *tabs, uint64_t stride,
+                                                 const uint32_t *mtab, wt_levels dst, uint32_t l)
+{
+    const uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t W = dst.words_per_level;
+    if (w >= W) return;
+    const uint64_t np = 1ull << l;
+    const uint64_t ne = np * count;
+    const uint32_t *ds = mtab + (uint64_t)count * (np - 1);
+    const bool wt = (dst.kind == WT_TREE);
+    const uint64_t b0 = w << 6;
+    const uint64_t we = min(b0 + 64, dst.n);
+    uint64_t val = 0;
+    uint64_t pos = b0;
+    while (pos < we) {
+        // the last (prefix, piece) interval, in the whole's order, starting
+        // at or before pos (never an empty one: it shares the next start)
+        uint64_t lo = 0, hi = ne;
+        while (hi - lo > 1) {
+            const uint64_t mid = (lo + hi) >> 1;
+            const uint32_t k = (uint32_t)(mid / count), c = (uint32_t)(mid % count);
+            const uint32_t p = wt ? k : rev_bits(k, l);
+            if (ds[(uint64_t)p * count + c] <= pos) lo = mid;
+            else hi = mid;
+        }
+        const uint32_t k = (uint32_t)(lo / count), c = (uint32_t)(lo % count);
+        const uint32_t p = wt ? k : rev_bits(k, l);
+        const uint32_t *tab = tabs + c * stride + ctab_off(l);
+        const uint64_t start = ds[(uint64_t)p * count + c];
+        const uint64_t src0 = wt ? tab[2 * np + p] : tab[p];  // start in the piece's own order
+        uint64_t end = start + tab[np + p];
+        if (end > we) end = we;
+        if (end <= pos) break;  // never for consistent tables
+        const uint32_t cnt = (uint32_t)(end - pos);
+        const uint64_t s = src0 + (pos - start);
+        const uint64_t *sb = parts[c].bits + (uint64_t)l * parts[c].words_per_level;
+        const uint32_t sh = (uint32_t)(s & 63);
+        uint64_t x = sb[s >> 6] >> sh;
+        if (sh && sh + cnt > 64) x |= sb[(s >> 6) + 1] << (64 - sh);
+        if (cnt < 64) x &= (1ull << cnt) - 1;
+        val |= x << (pos - b0);
+        pos = end;
+    }
+    dst.bits[(uint64_t)l * W + w] = val;
+}
+
+__global__ void k_mzeros(const wt_levels *__restrict__ parts, uint32_t count, wt_levels dst)
+{
+    for (uint32_t l = threadIdx.x; l < dst.lg_sigma; l += blockDim.x) {
+        uint64_t z = 0;
+        for (uint32_t c = 0; c < count; c++) z += parts[c].zeros[l];
+        dst.zeros[l] = z;
+    }
+}
+
 static inline uint32_t blocks_for(uint64_t n, uint32_t t) { return (uint32_t)((n + t - 1) / t); }
+
+hipError_t launch_merge(const wt_levels *d_parts, uint32_t count, uint32_t *d_tabs, uint64_t stride,
+                        uint32_t *d_mtab, const wt_levels &dst, const LaunchCtx &ctx)
+{
+    const uint32_t L = dst.lg_sigma;
+    for (uint32_t l = 0; l < L; l++)
+        hipLaunchKernelGGL(k_mwalk, dim3(blocks_for((1ull << l) * count, 256)), dim3(256), 0, ctx.stream,
+                           d_parts, count, d_tabs, stride, l);
+    hipLaunchKernelGGL(k_mstarts, dim3(L), dim3(1024), 0, ctx.stream, d_tabs, stride, count, dst.kind,
+                       d_mtab);
+    if (ctx.after) ctx.after(ctx.user, KID_WALK);
+    if (dst.words_per_level > 0)
+        for (uint32_t l = 0; l < L; l++)
+            hipLaunchKernelGGL(k_mgather, dim3(blocks_for(dst.words_per_level, 256)), dim3(256), 0,
+                               ctx.stream, d_parts, count, d_tabs, stride, d_mtab, dst, l);
+    hipLaunchKernelGGL(k_mzeros, dim3(1), dim3(64), 0, ctx.stream, d_parts, count, dst);
+    if (ctx.after) ctx.after(ctx.user, KID_GATHER);
+    return hipGetLastError();
+}
 
 hipError_t launch_convert_walk(const wt_levels &src, uint32_t *d_tab, uint32_t levels,
                                bool need_wm_starts, const LaunchCtx &ctx)
