@@ -69,6 +69,7 @@ def _bind(lib):
                                     _u64, _u64p]),
         "orc_sample_level": (_int, [_int, _vp, _u64, _u32, _u32, _u32, _u64p, _u64, _u8p]),
         "orc_map_wt_to_wm": (_int, [_vp, _u64, _u32, _u32, _u32, _u64p, _u64, _u64p]),
+        "orc_pointer_tree": (_int, [_vp, _u64, _u32, _u32, _u64p, _u64p, _u64]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -199,6 +200,26 @@ class Oracle:
         if rc != OK:
             raise OracleError(rc, "map_wt_to_wm")
         return out[: p.size]
+
+    def pointer_tree(self, text, L: int):
+        """Node table (uint64 [2^L - 1, 2]: first pool word, bits) and pool of
+        the pointer-based WT (node e = 2^l - 1 + p holds prefix p of length l)."""
+        t, b = self._text(text)
+        n = t.size
+        entries = (1 << L) - 1
+        nodes = np.zeros((max(entries, 1), 2), dtype=np.uint64)
+        pool_words = L * ((n + 63) // 64) + entries
+        pool = np.zeros(max(pool_words, 1), dtype=np.uint64)
+        rc = self.lib.orc_pointer_tree(t.ctypes.data, n, b, L, self._p(nodes, _u64p), self._p(pool, _u64p),
+                                       pool.size)
+        if rc != OK:
+            raise OracleError(rc, "pointer_tree")
+        return nodes[:entries].copy(), pool
+
+    def node_bits(self, nodes, pool, e: int):
+        """Bits (list of 0/1) of node e of a pointer_tree result."""
+        w0, h = int(nodes[e, 0]), int(nodes[e, 1])
+        return [int((int(pool[w0 + q // 64]) >> (q % 64)) & 1) for q in range(h)]
 
     def sample_level(self, kind: int, text, L: int, level: int, positions):
         t, b = self._text(text)

@@ -608,3 +608,52 @@ done:
     return rc;
 }
 
+
+/* ---- pointer-based wavelet tree (Section 2) ------------------------------ */
+
+/* Node (l, p) of the pointer-based tree is the node reached from the root by
+ * the l-bit prefix p; its bit vector holds bit(l, a) of every symbol a of T
+ * with prefix(l, a) = p, in text order.  Entry e = 2^l - 1 + p of `nodes`
+ * receives {first pool word, number of bits}; each node's bits start at bit
+ * 0 of a fresh pool word (LSB-first) and take ceil(bits / 64) words, the
+ * nodes one after the other in entry order.  Pool words not covered by a node
+ * are zero. */
+int orc_pointer_tree(const void *text, uint64_t n, uint32_t sym_bytes, uint32_t L, uint64_t *nodes,
+                     uint64_t *pool, uint64_t pool_words)
+{
+    int rc = orc_check_symbols(text, n, sym_bytes, L);
+    if (rc != ORC_OK) return rc;
+    if (L > 26) return ORC_EINVAL;
+    if (L == 0) return ORC_OK;
+    uint64_t entries = ((uint64_t)1 << L) - 1;
+    uint64_t *fill = (uint64_t *)calloc((size_t)entries, sizeof(uint64_t));
+    if (!fill) return ORC_ENOMEM;
+    /* node sizes: how many symbols carry each prefix */
+    for (uint64_t e = 0; e < entries; e++) nodes[2 * e + 1] = 0;
+    for (uint32_t l = 0; l < L; l++) {
+        uint64_t first = ((uint64_t)1 << l) - 1;
+        for (uint64_t i = 0; i < n; i++) nodes[2 * (first + prefix_of(L, l, sym_at(text, sym_bytes, i))) + 1]++;
+    }
+    /* runs of whole words, in entry order */
+    uint64_t w = 0;
+    for (uint64_t e = 0; e < entries; e++) {
+        nodes[2 * e] = w;
+        w += (nodes[2 * e + 1] + 63) / 64;
+    }
+    if (w > pool_words) {
+        free(fill);
+        return ORC_EINVAL;
+    }
+    memset(pool, 0, (size_t)(pool_words * sizeof(uint64_t)));
+    /* append each symbol's bit to its node on every level, in text order */
+    for (uint64_t i = 0; i < n; i++) {
+        uint32_t a = sym_at(text, sym_bytes, i);
+        for (uint32_t l = 0; l < L; l++) {
+            uint64_t e = ((uint64_t)1 << l) - 1 + prefix_of(L, l, a);
+            uint64_t q = fill[e]++;
+            if (bit_of(L, l, a)) pool[nodes[2 * e] + q / 64] |= (uint64_t)1 << (q % 64);
+        }
+    }
+    free(fill);
+    return ORC_OK;
+}

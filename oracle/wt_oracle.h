@@ -54,6 +54,11 @@ int orc_queries_walk(int kind, const uint64_t *bits, uint64_t W, const uint64_t 
 int orc_map_wt_to_wm(const void *text, uint64_t n, uint32_t sym_bytes, uint32_t L, uint32_t level,
                      const uint64_t *positions, uint64_t m, uint64_t *out);
 
+/* pointer-based WT: nodes[2e] = first pool word, nodes[2e+1] = bits of node
+ * e = 2^l - 1 + p (prefix p of length l); bits LSB-first from a fresh word */
+int orc_pointer_tree(const void *text, uint64_t n, uint32_t sym_bytes, uint32_t L, uint64_t *nodes,
+                     uint64_t *pool, uint64_t pool_words);
+
 /* bit `level` of the WT/WM at the given positions (0/1 per position) */
 int orc_sample_level(int kind, const void *text, uint64_t n, uint32_t sym_bytes, uint32_t L,
                      uint32_t level, const uint64_t *positions, uint64_t m, uint8_t *out);

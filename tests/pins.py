@@ -372,6 +372,45 @@ def check_map_wt_to_wm(o):
             assert all(bt[i] == bm[int(j[i])] for i in range(n)), (L, l)
 
 
+def check_pointer_tree(o):
+    """The pointer-based WT (Section 2): the hand-worked nodes of the running
+    example, every node against a filter of the text on tiny inputs, each
+    node's zeros and ones sizing its two children, whole-word runs in entry
+    order, and the nodes of a level side by side forming the WT level."""
+    g = read_golden()
+    T = np.array([int(x) for x in g["text"].split()], dtype=np.uint8)
+    nodes, pool = o.pointer_tree(T, 3)
+    want = g["ptree_nodes"].split()
+    assert ["".join(map(str, o.node_bits(nodes, pool, e))) for e in range(7)] == want
+    rng = np.random.default_rng(31)
+    cases = [(rng.integers(0, 1 << L, size=n).astype(np.uint16), L)
+             for L, n in ((1, 7), (2, 70), (3, 130), (4, 64), (5, 300), (7, 1000))]
+    cases.append((((np.arange(700) * 53) % 37 * 3 % 512).astype(np.uint16), 9))  # empty nodes
+    cases.append((np.zeros(0, dtype=np.uint8), 3))
+    for T, L in cases:
+        nodes, pool = o.pointer_tree(T, L)
+        wt, _ = o.build(WT, T, L)
+        w = 0
+        for l in range(L):
+            row = []
+            for p in range(1 << l):
+                e = (1 << l) - 1 + p
+                got = o.node_bits(nodes, pool, e)
+                if T.size <= 300:
+                    assert got == [bit(L, l, int(a)) for a in T if prefix(L, l, int(a)) == p], (L, l, p)
+                assert int(nodes[e, 0]) == w
+                w += (len(got) + 63) // 64
+                # bits past the node's length stay clear
+                if len(got) % 64:
+                    assert int(pool[int(nodes[e, 0]) + len(got) // 64]) >> (len(got) % 64) == 0
+                if l + 1 < L:
+                    assert int(nodes[2 * e + 1, 1]) == got.count(0)
+                    assert int(nodes[2 * e + 2, 1]) == got.count(1)
+                row += got
+            assert row == unpack(wt[l], T.size), (L, l)
+    assert int(nodes[0, 1]) == T.size
+
+
 def check_errors(o):
     import oracle
     T = np.array([0, 1, 8], dtype=np.uint8)
@@ -389,4 +428,4 @@ def check_errors(o):
 
 ALL_CHECKS = [check_golden, check_printed_small_facts, check_levels_brute, check_wide_symbols,
               check_invariants, check_queries, check_rank_select_bv, check_directory,
-              check_sample_level, check_map_wt_to_wm, check_errors]
+              check_sample_level, check_map_wt_to_wm, check_pointer_tree, check_errors]

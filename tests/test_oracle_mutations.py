@@ -54,6 +54,13 @@ MUTATIONS = {
     "map_wm_start_from_wt": ("out[q] = swm[lo] + (i - swt[lo]);", "out[q] = swt[lo] + (i - swt[lo]);"),
     # position map searches with the WM starts
     "map_search_wm_order": ("if (swt[mid] <= i) lo = mid;", "if (swm[mid] <= i) lo = mid;"),
+    # pointer tree: runs of floor instead of ceil words (overlapping nodes)
+    "ptree_runs_floor": ("w += (nodes[2 * e + 1] + 63) / 64;", "w += nodes[2 * e + 1] / 64;"),
+    # pointer tree: nodes of a level in bit-reversed (WM) order
+    "ptree_reversed_nodes": ("uint64_t e = ((uint64_t)1 << l) - 1 + prefix_of(L, l, a);",
+                             "uint64_t e = ((uint64_t)1 << l) - 1 + orc_reverse_bits(prefix_of(L, l, a), l);"),
+    # pointer tree: bits of a node in reverse text order
+    "ptree_reverse_text": ("uint64_t q = fill[e]++;", "uint64_t q = nodes[2 * e + 1] - 1 - fill[e]++;"),
     # WM select walk forgets the Z offset
     "walk_wm_select_z": ("p = b ? orc_select_bv(lv, n, p - zeros[l] + 1, 1)", "p = b ? orc_select_bv(lv, n, p + 1, 1)"),
 }
