@@ -482,6 +482,22 @@ def main():
         raise SystemExit("merged pieces differ from the direct build")
     conv["merge_8_pieces_ms"] = round(mg_ms, 3)
     del parts, merged
+    # export of the WT to node-local bit vectors (pointer-based tree): every
+    # sampled bit of every level must sit in its node at the same offset
+    (xn, xp), x_ms = timed(lambda: B.export_nodes(structs[B.WT_TREE]))
+    for lvl in range(L):
+        e0 = (1 << lvl) - 1
+        lens = xn[e0:e0 + (1 << lvl), 1]
+        starts = torch.cumsum(lens, 0) - lens
+        node = torch.searchsorted(starts, qpos, right=True) - 1
+        k = qpos - starts[node]
+        words = xn[e0 + node, 0] + (k >> 6)
+        got = (xp[words] >> (k & 63)) & 1
+        lv_words = structs[B.WT_TREE].buf[: L * W * 8].view(torch.int64).view(L, W)[lvl]
+        if not torch.equal(got, (lv_words[qpos >> 6] >> (qpos & 63)) & 1):
+            raise SystemExit(f"exported nodes of level {lvl} differ from the WT level")
+    conv["export_nodes_ms"] = round(x_ms, 3)
+    del xn, xp
     # both structures when both are wanted: build the WM, convert it to the WT
     conv["wm_build_plus_convert_ms"] = round(ms_per_step / 2 + conv["wm_to_wt_ms"], 3)
     conv["posmap_build_ms"] = round(pm_ms, 3)

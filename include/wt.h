@@ -218,6 +218,23 @@ int wt_merge(const wt_levels *parts, uint32_t count, wt_levels *dst, void *d_ws,
              hipStream_t stream);
 
 /*
+ * Export of a built WT to node-local bit vectors (Section 2: the
+ * pointer-based tree keeps one bit vector per node).  Node (l, p), the prefix
+ * p of length l, is entry e = 2^l - 1 + p of d_nodes (2^lg_sigma - 1 entries
+ * of two uint64: the first pool word of the node, and its number of bits);
+ * its children are entries 2e + 1 and 2e + 2.  The node's bits are the
+ * interval of p on WT level l, stored from bit 0 of its first pool word
+ * (LSB-first), the nodes' runs one after the other in entry order.
+ * wt_export_pool_words(n, lg_sigma) bounds the pool; the words past the last
+ * node's run within that bound receive zeros or nothing.  d_ws: workspace of
+ * wt_convert_workspace_bytes(n, lg_sigma).  Asynchronous on `stream`.
+ * WT_EINVAL if *wt is not a WT; WT_ENOTSUP for lg_sigma > WT_MAX_TREE_LEVELS.
+ */
+uint64_t wt_export_pool_words(uint64_t n, uint32_t lg_sigma);
+int wt_export_nodes(const wt_levels *wt, uint64_t *d_nodes, uint64_t *d_pool, uint64_t pool_words,
+                    void *d_ws, size_t ws_bytes, hipStream_t stream);
+
+/*
  * Position map of Lemma 5: the position j in WM level l of the bit at
  * position i of WT level l, in O(1) per query from
  *   U  the unary histogram 1^{c_0} 0 1^{c_1} 0 ... of the symbol counts

@@ -96,6 +96,8 @@ _SIGS = {
     "wt_convert": (_i, [_LP, _LP, _v, _sz, _v]),
     "wt_merge_workspace_bytes": (_sz, [_u64, _u32, _u32]),
     "wt_merge": (_i, [_LP, _u32, _LP, _v, _sz, _v]),
+    "wt_export_pool_words": (_u64, [_u64, _u32]),
+    "wt_export_nodes": (_i, [_LP, _v, _v, _u64, _v, _sz, _v]),
     "wt_posmap_bytes": (_sz, [_u64, _u32]),
     "wt_posmap_bind": (_i, [ctypes.POINTER(WtPosmap), _v, _sz, _u64, _u32]),
     "wt_posmap_build": (_i, [_LP, ctypes.POINTER(WtPosmap), _v, _sz, _v]),
@@ -311,6 +313,29 @@ def merge(parts, stream=None) -> Structure:
                    _stream_handle(stream)), "wt_merge")
     dst._ws = ws
     return dst
+
+
+def export_nodes(s: Structure, stream=None):
+    """Node-local bit vectors of a built WT (wt_export_nodes): a node table
+    (int64 [2^L - 1, 2]: first pool word, bits; node 2^l - 1 + p is prefix p
+    of length l) and the pool of words (int64) holding every node's bits from
+    a fresh word."""
+    torch = _torch()
+    L = s.L
+    dev = s.buf.device
+    entries = (1 << L) - 1
+    nodes = torch.empty((max(entries, 1), 2), dtype=torch.int64, device=dev)
+    pool_words = int(wt_export_pool_words(s.n, L))
+    pool = torch.empty(max(pool_words, 1), dtype=torch.int64, device=dev)
+    need = int(wt_convert_workspace_bytes(s.n, L))
+    if need == 0:
+        raise WtError(WT_ENOTSUP, "wt_convert_workspace_bytes")
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    check(wt_export_nodes(ctypes.byref(s.view), ctypes.c_void_p(nodes.data_ptr()),
+                          ctypes.c_void_p(pool.data_ptr()), pool_words, ctypes.c_void_p(ws.data_ptr()), need,
+                          _stream_handle(stream)), "wt_export_nodes")
+    s._export_ws = ws
+    return nodes[:entries], pool
 
 
 class PosMap:

@@ -597,6 +597,34 @@ int wt_merge(const wt_levels *parts, uint32_t count, wt_levels *dst, void *d_ws,
     return WT_OK;
 }
 
+uint64_t wt_export_pool_words(uint64_t n, uint32_t lg_sigma)
+{
+    if (lg_sigma > WT_MAX_TREE_LEVELS || lg_sigma == 0) return 0;
+    // a node of h bits takes ceil(h/64) <= h/64 + 1 words; a level holds n bits
+    return (uint64_t)lg_sigma * cdiv64(n, 64) + ((1ull << lg_sigma) - 1);
+}
+
+int wt_export_nodes(const wt_levels *wt, uint64_t *d_nodes, uint64_t *d_pool, uint64_t pool_words,
+                    void *d_ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (!view_ok(wt) || wt->kind != WT_TREE || !d_nodes || !d_pool || !d_ws) return WT_EINVAL;
+    const uint32_t L = wt->lg_sigma;
+    if (L > WT_MAX_TREE_LEVELS) return WT_ENOTSUP;
+    if (L == 0) return WT_OK;
+    if (pool_words < wt_export_pool_words(wt->n, L)) return WT_ENOSPACE;
+    const size_t need = wt_convert_workspace_bytes(wt->n, L);
+    if (need == 0) return WT_ENOTSUP;
+    if (ws_bytes < need) return WT_ENOSPACE;
+    ConvWs w;
+    conv_plan(wt->n, L, (uint8_t *)align_up((uintptr_t)d_ws, 256), &w);
+    LaunchCtx ctx{stream, nullptr, nullptr};
+    if (launch_convert_walk(*wt, w.tab, L, false, ctx) != hipSuccess) return WT_EHIP;
+    // pool words past the nodes' runs are left as they are
+    const uint64_t used = wt_export_pool_words(wt->n, L);
+    if (launch_export_nodes(*wt, w.tab, d_nodes, d_pool, used, ctx) != hipSuccess) return WT_EHIP;
+    return WT_OK;
+}
+
 struct PmLayout {
     uint64_t ulen, uw, rs, ss, o_rd, o_s0, o_s1, o_x, total;
 };

@@ -337,7 +337,93 @@ __global__ void k_mzeros(const wt_levels *__restrict__ parts, uint32_t count, wt
     }
 }
 
+// ---------------------------------------------------------------------------
+// Export to node-local bit vectors (Section 2: the pointer-based WT keeps one
+// bit vector per node; the level-wise WT concatenates a level's nodes).  Node
+// (l, p) is entry 2^l - 1 + p of the node table (children of entry e at 2e+1
+// and 2e+2); its bits are the interval of prefix p on WT level l, copied to a
+// word-aligned run of the pool so that every node's bit vector starts at
+// bit 0 of a word.
+
+// pool words of every node, then their zero-based prefix sum (one block):
+// nodes[e] = {first pool word, bits}
+__global__ __launch_bounds__(1024) void k_xoffsets(const uint32_t *tab, uint32_t L, uint64_t *nodes)
+{
+    __shared__ uint64_t part[1024];
+    const uint64_t ne = (1ull << L) - 1;
+    const uint32_t t = threadIdx.x;
+    const uint64_t per = (ne + 1023) / 1024;
+    const uint64_t e0 = t * per, e1 = min(ne, e0 + per);
+    auto len_of = [&](uint64_t e) -> uint64_t {
+        const uint32_t l = 63 - __clzll(e + 1);
+        const uint64_t p = e - ((1ull << l) - 1);
+        return tab[ctab_off(l) + (1ull << l) + p];
+    };
+    uint64_t s = 0;
+    for (uint64_t e = e0; e < e1; e++) s += (len_of(e) + 63) >> 6;
+    part[t] = s;
+    __syncthreads();
+    for (uint32_t off = 1; off < 1024; off <<= 1) {
+        const uint64_t x = (t >= off) ? part[t - off] : 0ull;
+        __syncthreads();
+        part[t] += x;
+        __syncthreads();
+    }
+    uint64_t run = part[t] - s;
+    for (uint64_t e = e0; e < e1; e++) {
+        const uint64_t h = len_of(e);
+        nodes[2 * e] = run;
+        nodes[2 * e + 1] = h;
+        run += (h + 63) >> 6;
+    }
+}
+
+// pool word q: the node whose run holds it (binary search over the node
+// table), and the 64 bits of its interval at that offset
+__global__ __launch_bounds__(256) void k_xgather(wt_levels wt, const uint32_t *tab, const uint64_t *nodes,
+                                                 uint64_t *pool, uint64_t pool_words)
+{
+    const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= pool_words) return;
+    const uint64_t ne = (1ull << wt.lg_sigma) - 1;
+    // last node whose run starts at or before q (empty nodes share the next
+    // node's start, so the last one is not empty)
+    uint64_t lo = 0, hi = ne;
+    while (hi - lo > 1) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (nodes[2 * mid] <= q) lo = mid;
+        else hi = mid;
+    }
+    const uint64_t h = nodes[2 * lo + 1];
+    const uint64_t k = q - nodes[2 * lo];  // word of the node
+    if (k * 64 >= h) {                      // never for a consistent table
+        pool[q] = 0;
+        return;
+    }
+    const uint32_t l = 63 - __clzll(lo + 1);
+    const uint64_t p = lo - ((1ull << l) - 1);
+    const uint64_t s = (uint64_t)tab[ctab_off(l) + 2 * (1ull << l) + p] + k * 64;  // WT position
+    const uint32_t cnt = (uint32_t)min<uint64_t>(64, h - k * 64);
+    const uint64_t *sb = wt.bits + (uint64_t)l * wt.words_per_level;
+    const uint32_t sh = (uint32_t)(s & 63);
+    uint64_t x = sb[s >> 6] >> sh;
+    if (sh && sh + cnt > 64) x |= sb[(s >> 6) + 1] << (64 - sh);
+    if (cnt < 64) x &= (1ull << cnt) - 1;
+    pool[q] = x;
+}
+
 static inline uint32_t blocks_for(uint64_t n, uint32_t t) { return (uint32_t)((n + t - 1) / t); }
+
+hipError_t launch_export_nodes(const wt_levels &wt, const uint32_t *d_tab, uint64_t *d_nodes,
+                               uint64_t *d_pool, uint64_t pool_words, const LaunchCtx &ctx)
+{
+    hipLaunchKernelGGL(k_xoffsets, dim3(1), dim3(1024), 0, ctx.stream, d_tab, wt.lg_sigma, d_nodes);
+    if (pool_words)
+        hipLaunchKernelGGL(k_xgather, dim3(blocks_for(pool_words, 256)), dim3(256), 0, ctx.stream, wt, d_tab,
+                           d_nodes, d_pool, pool_words);
+    if (ctx.after) ctx.after(ctx.user, KID_GATHER);
+    return hipGetLastError();
+}
 
 hipError_t launch_merge(const wt_levels *d_parts, uint32_t count, uint32_t *d_tabs, uint64_t stride,
                         uint32_t *d_mtab, const wt_levels &dst, const LaunchCtx &ctx)

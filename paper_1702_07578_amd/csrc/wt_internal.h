@@ -146,6 +146,8 @@ hipError_t launch_convert_gather(const wt_levels &src, const wt_levels &dst, con
                                  const LaunchCtx &ctx);
 hipError_t launch_merge(const wt_levels *d_parts, uint32_t count, uint32_t *d_tabs, uint64_t stride,
                         uint32_t *d_mtab, const wt_levels &dst, const LaunchCtx &ctx);
+hipError_t launch_export_nodes(const wt_levels &wt, const uint32_t *d_tab, uint64_t *d_nodes,
+                               uint64_t *d_pool, uint64_t pool_words, const LaunchCtx &ctx);
 hipError_t launch_posmap_fill(const wt_posmap &m, const uint32_t *d_tab, const LaunchCtx &ctx);
 hipError_t launch_posmap_query(const wt_posmap &m, uint32_t level, const uint64_t *d_pos,
                                uint64_t count, uint64_t *d_out, const LaunchCtx &ctx);

@@ -84,3 +84,22 @@ def test_conversion_and_position_map_sizes():
     assert B.wt_levels_bind(ctypes.byref(a), ctypes.c_void_p(1 << 20), out, 1000, 8, 0) == B.WT_OK
     assert B.wt_levels_bind(ctypes.byref(b), ctypes.c_void_p(1 << 24), out, 1000, 8, 0) == B.WT_OK
     assert B.wt_convert(ctypes.byref(a), ctypes.byref(b), ctypes.c_void_p(1 << 28), 1 << 20, None) == B.WT_EINVAL
+
+
+def test_export_sizes_and_refusals():
+    """Pool bound of the node-local export and its refusals before any
+    device work."""
+    from paper_1702_07578_amd import binding as B
+    assert B.wt_export_pool_words(1000, 8) == 8 * 16 + 255
+    assert B.wt_export_pool_words(1000, 0) == 0
+    assert B.wt_export_pool_words(1000, B.WT_MAX_TREE_LEVELS + 1) == 0
+    v = B.WtLevels()
+    out = B.wt_output_bytes(1000, 8)
+    fake = ctypes.c_void_p(1 << 20)
+    assert B.wt_levels_bind(ctypes.byref(v), fake, out, 1000, 8, 1) == B.WT_OK
+    ws = B.wt_convert_workspace_bytes(1000, 8)
+    assert B.wt_export_nodes(ctypes.byref(v), fake, fake, 1 << 12, fake, ws, None) == B.WT_EINVAL  # a WM
+    assert B.wt_levels_bind(ctypes.byref(v), fake, out, 1000, 8, 0) == B.WT_OK
+    assert B.wt_export_nodes(ctypes.byref(v), fake, fake, 100, fake, ws, None) == B.WT_ENOSPACE
+    assert B.wt_export_nodes(ctypes.byref(v), fake, fake, 1 << 12, fake, ws - 1, None) == B.WT_ENOSPACE
+    assert B.wt_export_nodes(ctypes.byref(v), None, fake, 1 << 12, fake, ws, None) == B.WT_EINVAL
