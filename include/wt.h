@@ -201,7 +201,7 @@ size_t wt_convert_workspace_bytes(uint64_t n, uint32_t lg_sigma);
 int wt_convert(const wt_levels *src, wt_levels *dst, void *d_ws, size_t ws_bytes, hipStream_t stream);
 
 /*
- * Merge of partial structures (Section 3.3, domain decomposition): parts[c]
+ * Merge of partial structures (Section 3.2, domain decomposition; Lemma 4): parts[c]
  * (host array of bound views, same kind and lg_sigma, built on this device)
  * hold the structures of consecutive pieces of a text; *dst (same kind and
  * lg_sigma, n = the pieces' total) receives the structure of the whole text:

@@ -188,7 +188,7 @@ __global__ __launch_bounds__(256) void k_cstarts(wt_posmap m, const uint32_t *ta
 }
 
 // ---------------------------------------------------------------------------
-// Merging partial structures (Section 3.3, domain decomposition): `count`
+// Merging partial structures (Section 3.2, domain decomposition; Lemma 4): `count`
 // structures of the same kind built from consecutive pieces of a text.  On
 // level l the whole text's interval of prefix k is the concatenation, piece
 // by piece, of the pieces' intervals of k (text order is piece order), and

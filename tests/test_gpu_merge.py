@@ -1,5 +1,5 @@
 """Merging the structures of consecutive pieces of a text (domain
-decomposition, Section 3.3) gives the structure of the whole text: levels,
+decomposition, Section 3.2, Lemma 4) gives the structure of the whole text: levels,
 Z and directories equal the oracle's build of the concatenation."""
 import numpy as np
 import pytest
