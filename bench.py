@@ -498,6 +498,17 @@ def main():
             raise SystemExit(f"exported nodes of level {lvl} differ from the WT level")
     conv["export_nodes_ms"] = round(x_ms, 3)
     del xn, xp
+    # the second build strategy (a counting sort of the text per level): its
+    # time per build, and equality with the default build
+    ps_ms = {}
+    for k, name in ((B.WT_TREE, "sort_build_wt_ms"), (B.WT_MATRIX, "sort_build_wm_ms")):
+        ps_out = B.Structure(n, L, k, device=dev)
+        ps_ws = torch.empty(int(B.wt_ps_workspace_bytes(n, b, L)), dtype=torch.uint8, device=dev)
+        _, t_ms = timed(lambda: B.ps_build(d_text, n, b, L, k, ws=ps_ws, out=ps_out))
+        if not same_levels(ps_out, structs[k]) or ps_out.status() != 0:
+            raise SystemExit(f"sorting build of kind {k} differs from the default build")
+        ps_ms[name] = round(t_ms, 3)
+        del ps_out, ps_ws
     # both structures when both are wanted: build the WM, convert it to the WT
     conv["wm_build_plus_convert_ms"] = round(ms_per_step / 2 + conv["wm_to_wt_ms"], 3)
     conv["posmap_build_ms"] = round(pm_ms, 3)
@@ -536,6 +547,7 @@ def main():
         "dominant_kernel": dom,
         "queries_per_s": round(q_per_s, 1),
         "conversion": conv,
+        "sort_strategy": ps_ms,
     }
     print(json.dumps(out), flush=True)
 

@@ -218,6 +218,26 @@ int wt_merge(const wt_levels *parts, uint32_t count, wt_levels *dst, void *d_ws,
              hipStream_t stream);
 
 /*
+ * Construction by sorting (Section 3.2, construction using sorting,
+ * Algorithm 2; the WM version of Section 5.1): the second build strategy,
+ * with the same result as wt_build_tuned (levels, Z, directories, status).
+ * The text is cut into chunks; the chunks' histograms of the full symbols are
+ * counted once; then, from the last level up, the histograms of the level's
+ * prefixes are merged from the next level's, one zero-based prefix sum over
+ * (prefix, chunk) in prefix order (WT) or bit-reversed prefix order (WM)
+ * gives each chunk's start per prefix, a stable counting sort by the level's
+ * prefix writes a sorted copy of the text, and the level's bits are bit l of
+ * that copy.  Level 0 is read from the text.
+ * wt_ps_workspace_bytes: workspace bytes (about n * sym_bytes for the sorted
+ * copy plus the chunk tables), 0 when unsupported.  lg_sigma is at most 12
+ * (WT_ENOTSUP above); other argument rules, outputs and error reporting as for
+ * wt_build_tuned.  d_text must be aligned to sym_bytes.  Asynchronous.
+ */
+size_t wt_ps_workspace_bytes(uint64_t n, uint32_t sym_bytes, uint32_t lg_sigma);
+int wt_ps_build(wt_kind kind, const void *d_text, uint64_t n, uint32_t sym_bytes, uint32_t lg_sigma,
+                wt_levels *out, void *d_ws, size_t ws_bytes, hipStream_t stream);
+
+/*
  * Export of a built WT to node-local bit vectors (Section 2: the
  * pointer-based tree keeps one bit vector per node).  Node (l, p), the prefix
  * p of length l, is entry e = 2^l - 1 + p of d_nodes (2^lg_sigma - 1 entries

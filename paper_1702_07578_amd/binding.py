@@ -96,6 +96,8 @@ _SIGS = {
     "wt_convert": (_i, [_LP, _LP, _v, _sz, _v]),
     "wt_merge_workspace_bytes": (_sz, [_u64, _u32, _u32]),
     "wt_merge": (_i, [_LP, _u32, _LP, _v, _sz, _v]),
+    "wt_ps_workspace_bytes": (_sz, [_u64, _u32, _u32]),
+    "wt_ps_build": (_i, [_i, _v, _u64, _u32, _u32, _LP, _v, _sz, _v]),
     "wt_export_pool_words": (_u64, [_u64, _u32]),
     "wt_export_nodes": (_i, [_LP, _v, _v, _u64, _v, _sz, _v]),
     "wt_posmap_bytes": (_sz, [_u64, _u32]),
@@ -256,6 +258,27 @@ def build(d_text, n: int, sym_bytes: int, L: int, kind: int, tune=None, stream=N
                          ctypes.c_void_p(ws.data_ptr()), ws.numel(), _tune_ptr(tune),
                          _stream_handle(stream)), "wt_build_tuned")
     s._ws = ws  # keep alive until the caller synchronises
+    return s
+
+
+def ps_build(d_text, n: int, sym_bytes: int, L: int, kind: int, stream=None, ws=None,
+             out: Structure | None = None) -> Structure:
+    """Build by sorting (wt_ps_build): the same structure as build(), by a
+    counting sort of the text per level."""
+    torch = _torch()
+    dev = d_text.device
+    s = out if out is not None else Structure(n, L, kind, device=dev)
+    need = int(wt_ps_workspace_bytes(n, sym_bytes, L))
+    if need == 0:
+        check(wt_ps_build(kind, ctypes.c_void_p(d_text.data_ptr() if n else 0), n, sym_bytes, L,
+                          ctypes.byref(s.view), None, 0, None), "wt_ps_build")
+        raise WtError(WT_EINVAL, "wt_ps_workspace_bytes")
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    ptr = ctypes.c_void_p(d_text.data_ptr()) if n > 0 else ctypes.c_void_p(ws.data_ptr())
+    check(wt_ps_build(kind, ptr, n, sym_bytes, L, ctypes.byref(s.view), ctypes.c_void_p(ws.data_ptr()),
+                      ws.numel(), _stream_handle(stream)), "wt_ps_build")
+    s._ws = ws
     return s
 
 

@@ -597,6 +597,104 @@ int wt_merge(const wt_levels *parts, uint32_t count, wt_levels *dst, void *d_ws,
     return WT_OK;
 }
 
+// ---- construction by sorting ------------------------------------------------
+
+// chunks: at most kTargetRanges, and few enough that a level's (prefix, chunk)
+// table stays within 2^23 entries (the prefix sum's two-level reach)
+static void ps_chunks(uint64_t n, uint32_t L, uint32_t *P, uint64_t *C)
+{
+    const uint64_t pmax = std::max<uint64_t>(1, std::min<uint64_t>(kTargetRanges, (1ull << 23) >> (L ? L - 1 : 0)));
+    const uint64_t c = align_up(std::max<uint64_t>(cdiv64(std::max<uint64_t>(n, 1), pmax), 1), 256);
+    *C = c;
+    *P = (uint32_t)std::max<uint64_t>(1, cdiv64(n, c));
+}
+
+struct PsWs {
+    TextDesc *desc;
+    uint16_t *dir_bc;
+    uint32_t *dir_cs;
+    uint32_t *H0, *H1, *bsum;
+    void *sorted;
+};
+
+static uint64_t ps_plan(uint64_t n, uint32_t b, uint32_t L, uint8_t *base, PsWs *w)
+{
+    uint32_t P;
+    uint64_t C;
+    ps_chunks(n, L, &P, &C);
+    const uint64_t nb = words_per_level(n) / 8;
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) {
+        const uint64_t o = off;
+        off = align_up(off + std::max<uint64_t>(bytes, 1), 256);
+        return o;
+    };
+    const uint64_t o_desc = take(sizeof(TextDesc));
+    const uint64_t o_bc = take((uint64_t)L * nb * 2);
+    const uint64_t o_cs = take((uint64_t)L * cdiv64(nb, kDirChunk) * 4);
+    const uint64_t o_h0 = take(((uint64_t)P << L) * 4);
+    const uint64_t o_h1 = take(((uint64_t)P << L) * 4);
+    const uint64_t o_bs = take(4096 * 4);
+    const uint64_t o_sorted = take(n * b + 16);
+    if (w) {
+        w->desc = (TextDesc *)(base + o_desc);
+        w->dir_bc = (uint16_t *)(base + o_bc);
+        w->dir_cs = (uint32_t *)(base + o_cs);
+        w->H0 = (uint32_t *)(base + o_h0);
+        w->H1 = (uint32_t *)(base + o_h1);
+        w->bsum = (uint32_t *)(base + o_bs);
+        w->sorted = base + o_sorted;
+    }
+    return off + 256;
+}
+
+size_t wt_ps_workspace_bytes(uint64_t n, uint32_t sym_bytes, uint32_t lg_sigma)
+{
+    if (check_args(n, sym_bytes, lg_sigma, WT_MATRIX) != WT_OK || lg_sigma > kPsMaxLevels) return 0;
+    return ps_plan(n, sym_bytes, lg_sigma, nullptr, nullptr);
+}
+
+int wt_ps_build(wt_kind kind, const void *d_text, uint64_t n, uint32_t sym_bytes, uint32_t lg_sigma,
+                wt_levels *out, void *d_ws, size_t ws_bytes, hipStream_t stream)
+{
+    int rc = check_args(n, sym_bytes, lg_sigma, kind);
+    if (rc != WT_OK) return rc;
+    if (lg_sigma > kPsMaxLevels) return WT_ENOTSUP;
+    if ((rc = check_out(out, n, lg_sigma, kind)) != WT_OK) return rc;
+    if (!d_ws || (n > 0 && !d_text)) return WT_EINVAL;
+    if (((uintptr_t)d_text % sym_bytes) != 0) return WT_EINVAL;
+    const size_t need = wt_ps_workspace_bytes(n, sym_bytes, lg_sigma);
+    if (ws_bytes < need) return WT_ENOSPACE;
+    const uint32_t L = lg_sigma;
+    PsWs w;
+    ps_plan(n, sym_bytes, L, (uint8_t *)align_up((uintptr_t)d_ws, 256), &w);
+    ConvWs cw{};
+    cw.dir_bc = w.dir_bc;
+    cw.dir_cs = w.dir_cs;
+    LaunchCtx ctx{stream, nullptr, nullptr};
+    TextDesc d = dir_desc(n, L, out->bits, out->rank_dir, out->sel0, out->sel1, out->zeros, out->status, cw);
+    if (launch_init(d, w.desc, ctx) != hipSuccess) return WT_EHIP;
+    if (L == 0) return WT_OK;
+    PsDesc p{};
+    p.text = d_text;
+    p.n = n;
+    p.b = sym_bytes;
+    p.L = L;
+    p.kind = kind;
+    ps_chunks(n, L, &p.P, &p.C);
+    p.H0 = w.H0;
+    p.H1 = w.H1;
+    p.bsum = w.bsum;
+    p.sorted = w.sorted;
+    p.bits = out->bits;
+    p.W = out->words_per_level;
+    p.zeros = out->zeros;
+    p.status = out->status;
+    if (launch_ps(p, ctx) != hipSuccess) return WT_EHIP;
+    if (launch_dirs(w.desc, nullptr, 1, L * d.dir_chunks, L, false, 0, ctx) != hipSuccess) return WT_EHIP;
+    return WT_OK;
+}
+
 uint64_t wt_export_pool_words(uint64_t n, uint32_t lg_sigma)
 {
     if (lg_sigma > WT_MAX_TREE_LEVELS || lg_sigma == 0) return 0;

@@ -69,6 +69,23 @@ struct TextDesc {
     uint32_t *dir_cs;      // [Lall][dir_chunks] chunk sums -> prefixes
 };
 
+// Construction by sorting (the second strategy): text cut into P chunks of C
+// symbols; H0/H1 hold chunk histograms [prefix][chunk] (2^L * P entries
+// each), bsum the prefix sum's block sums, sorted the sorted copy (n symbols).
+constexpr uint32_t kPsMaxLevels = 12;
+struct PsDesc {
+    const void *text;
+    uint64_t n;
+    uint32_t b, L, kind, P;
+    uint64_t C;
+    uint32_t *H0, *H1, *bsum;
+    void *sorted;
+    uint64_t *bits;  // level l at bits + l * W
+    uint64_t W;
+    uint64_t *zeros;
+    int32_t *status;
+};
+
 // Host-side plan of one text: the descriptor plus workspace size.
 struct Plan {
     TextDesc d;
@@ -148,6 +165,7 @@ hipError_t launch_merge(const wt_levels *d_parts, uint32_t count, uint32_t *d_ta
                         uint32_t *d_mtab, const wt_levels &dst, const LaunchCtx &ctx);
 hipError_t launch_export_nodes(const wt_levels &wt, const uint32_t *d_tab, uint64_t *d_nodes,
                                uint64_t *d_pool, uint64_t pool_words, const LaunchCtx &ctx);
+hipError_t launch_ps(const PsDesc &d, const LaunchCtx &ctx);
 hipError_t launch_posmap_fill(const wt_posmap &m, const uint32_t *d_tab, const LaunchCtx &ctx);
 hipError_t launch_posmap_query(const wt_posmap &m, uint32_t level, const uint64_t *d_pos,
                                uint64_t count, uint64_t *d_out, const LaunchCtx &ctx);
