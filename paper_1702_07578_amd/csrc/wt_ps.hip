@@ -32,27 +32,55 @@ __device__ inline uint32_t sym_load(const void *p, uint64_t i)
 
 // ---------------------------------------------------------------------------
 // chunk histograms of the full symbols (and the range check); one block per
-// chunk, Hist[q * P + c]
+// chunk, Hist[q * P + c].  Up to 8 interleaved copies of the histogram in LDS
+// (fewer for large alphabets) spread the atomics of frequent symbols; 16-byte
+// loads when the text is 16-byte aligned (chunk starts are multiples of 256
+// symbols).
 template <typename E>
-__global__ __launch_bounds__(256) void k_ps_hist(PsDesc d)
+__global__ __launch_bounds__(256) void k_ps_hist(PsDesc d, bool vec)
 {
     extern __shared__ uint32_t hist[];
-    const uint32_t c = blockIdx.x;
+    constexpr uint32_t per = 16 / sizeof(E);
+    const uint32_t c = blockIdx.x, t = threadIdx.x;
     const uint32_t ns = 1u << d.L;
-    for (uint32_t q = threadIdx.x; q < ns; q += blockDim.x) hist[q] = 0;
+    const uint32_t copies = ns <= 512 ? 8u : (4096u >> d.L);
+    for (uint32_t q = t; q < ns * copies; q += 256) hist[q] = 0;
     __syncthreads();
     const uint64_t i0 = (uint64_t)c * d.C;
     const uint64_t i1 = min(d.n, i0 + d.C);
-    const uint32_t mask = ns - 1;
+    const uint32_t mask = ns - 1, cp = t & (copies - 1);
     bool bad = false;
-    for (uint64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    uint64_t tail = i0;
+    if (vec) {
+        const uint64_t units = (i1 - i0) / per;
+        const uint4 *src = (const uint4 *)((const E *)d.text + i0);
+        for (uint64_t u = t; u < units; u += 256) {
+            const uint4 v = src[u];
+            const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (uint32_t k = 0; k < 4; k++) {
+#pragma unroll
+                for (uint32_t s = 0; s < 4 / sizeof(E); s++) {
+                    const uint32_t a = sizeof(E) == 4 ? w4[k] : (w4[k] >> (s * 8 * sizeof(E))) & ((1u << (8 * sizeof(E))) - 1);
+                    bad |= (d.L < 32) && (a >> d.L) != 0;
+                    atomicAdd(&hist[(a & mask) * copies + cp], 1u);
+                }
+            }
+        }
+        tail = i0 + units * per;
+    }
+    for (uint64_t i = tail + t; i < i1; i += 256) {
         const uint32_t a = sym_load<E>(d.text, i);
         bad |= (d.L < 32) && (a >> d.L) != 0;
-        atomicAdd(&hist[a & mask], 1u);
+        atomicAdd(&hist[(a & mask) * copies + cp], 1u);
     }
     if (bad) atomicExch(d.status, (int32_t)WT_ERANGE);
     __syncthreads();
-    for (uint32_t q = threadIdx.x; q < ns; q += blockDim.x) d.H0[(uint64_t)q * d.P + c] = hist[q];
+    for (uint32_t q = t; q < ns; q += 256) {
+        uint32_t x = 0;
+        for (uint32_t k = 0; k < copies; k++) x += hist[q * copies + k];
+        d.H0[(uint64_t)q * d.P + c] = x;
+    }
 }
 
 // histogram of the l-bit prefixes from that of the (l+1)-bit prefixes
@@ -149,55 +177,141 @@ __global__ __launch_bounds__(1024) void k_ps_scan_down(uint32_t *H, const uint32
 }
 
 // ---------------------------------------------------------------------------
-// stable counting sort of the text by the l-bit prefix (l >= 1): one wave per
-// chunk; the wave's cursors (2^l entries) in LDS
+// stable counting sort of the text by the l-bit prefix (l >= 1): one block
+// per chunk, the chunk walked in segments of kPsSeg symbols.  Per segment:
+//   1. wave w ranks the symbols of its quarter among equal prefixes (ballots
+//      over the prefix bits, in text order) and counts them per prefix;
+//   2. per prefix, the waves' offsets and the prefix's start in the segment
+//      sorted by prefix (a scan over the prefixes);
+//   3. the symbols go to that sorted order in LDS;
+//   4. the staged segment is written out: a symbol at staged position p with
+//      prefix q goes to cursor[q] + (p - start of q), so equal prefixes leave
+//      as runs of consecutive addresses;
+//   5. every cursor moves past its prefix's symbols of the segment.
+constexpr uint32_t kPsSeg = 4096;
+constexpr uint32_t kPsPer = kPsSeg / 256;  // symbols per lane and segment
+
+// exclusive prefix sum over the 256 threads of a block; returns the total
+__device__ inline uint32_t block256_exscan(uint32_t v, uint32_t *wsum, uint32_t &total)
+{
+    const uint32_t w = threadIdx.x >> 6;
+    const uint32_t inc = wave_incl_scan(v);
+    if ((threadIdx.x & 63) == 63) wsum[w] = inc;
+    __syncthreads();
+    uint32_t before = 0;
+    for (uint32_t k = 0; k < w; k++) before += wsum[k];
+    total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    __syncthreads();
+    return before + inc - v;
+}
+
 template <typename E>
 __global__ __launch_bounds__(256) void k_ps_sort(PsDesc d, uint32_t l, const uint32_t *__restrict__ B)
 {
-    extern __shared__ uint32_t cursors[];
-    const uint32_t lane = lane_id();
-    const uint32_t w = threadIdx.x >> 6;
-    const uint32_t c = blockIdx.x * 4 + w;
-    if (c >= d.P) return;  // the whole wave leaves; no block-wide barrier follows
+    extern __shared__ uint32_t sm[];
+    __shared__ uint32_t wsum[4];
     const uint32_t nq = 1u << l;
-    uint32_t *cur = cursors + w * nq;
-    for (uint32_t q = lane; q < nq; q += 64) cur[q] = B[(uint64_t)q * d.P + c];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    uint32_t *cursor = sm;             // [nq]: next global position of prefix q
+    uint32_t *sstart = cursor + nq;    // [nq]: start of q in the staged segment
+    uint16_t *cnt = (uint16_t *)(sstart + nq);  // [4][nq]: per wave counts, then offsets
+    E *stage = (E *)(sm + 4 * nq);     // [kPsSeg], 16-byte aligned
+    const uint32_t t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const uint32_t c = blockIdx.x;
+    for (uint32_t q = t; q < nq; q += 256) {
+        cursor[q] = B[(uint64_t)q * d.P + c];
+        cnt[q] = cnt[nq + q] = cnt[2 * nq + q] = cnt[3 * nq + q] = 0;
+    }
+    __syncthreads();
     const uint64_t i0 = (uint64_t)c * d.C;
     const uint64_t i1 = min(d.n, i0 + d.C);
     const uint32_t shift = d.L - l;
-    const uint64_t lt = (1ull << lane) - 1;  // lanes below this one
+    const uint64_t lt = (1ull << lane) - 1;
+    const uint32_t per = (nq + 255) / 256;  // prefixes per thread in the scan
     E *out = (E *)d.sorted;
-    for (uint64_t s0 = i0; s0 < i1; s0 += 256) {
-        uint32_t a[4];
-        bool ok[4];
+    uint16_t *mycnt = cnt + w * nq;
+    for (uint64_t seg = i0; seg < i1; seg += kPsSeg) {
+        const uint32_t len = (uint32_t)min<uint64_t>(kPsSeg, i1 - seg);
+        // 1. ranks within the wave's quarter
+        uint32_t a[kPsPer], rk[kPsPer];
+        const uint64_t q0 = seg + w * (kPsSeg / 4);
 #pragma unroll
-        for (uint32_t j = 0; j < 4; j++) {
-            const uint64_t i = s0 + j * 64 + lane;
-            ok[j] = i < i1;
-            a[j] = ok[j] ? sym_load<E>(d.text, i) : 0u;
+        for (uint32_t j = 0; j < kPsPer; j++) {
+            const uint64_t i = q0 + j * 64 + lane;
+            a[j] = (i < seg + len) ? sym_load<E>(d.text, i) : 0u;
         }
 #pragma unroll
-        for (uint32_t j = 0; j < 4; j++) {
-            if (s0 + j * 64 >= i1) break;  // uniform
+        for (uint32_t j = 0; j < kPsPer; j++) {
+            const bool ok = q0 + j * 64 + lane < seg + len;
             const uint32_t q = (a[j] >> shift) & (nq - 1);
-            // lanes holding a symbol of the same prefix (multi-split by ballots)
-            uint64_t peers = __ballot(ok[j]);
+            uint64_t peers = __ballot(ok);
             for (uint32_t k = 0; k < l; k++) {
                 const bool bit = (q >> k) & 1u;
                 const uint64_t m = __ballot(bit);
                 peers &= bit ? m : ~m;
             }
             const uint32_t rank = (uint32_t)__popcll(peers & lt);
-            const uint32_t cnt = (uint32_t)__popcll(peers);
-            if (ok[j]) {
-                const uint32_t base = cur[q];
-                out[base + rank] = (E)a[j];
-                if (rank + 1 == cnt) cur[q] = base + cnt;  // the last lane of the prefix moves its cursor
+            const uint32_t num = (uint32_t)__popcll(peers);
+            rk[j] = 0;
+            if (ok) {
+                const uint32_t base = mycnt[q];
+                rk[j] = base + rank;
+                if (rank + 1 == num) mycnt[q] = (uint16_t)(base + num);
             }
         }
+        __syncthreads();
+        // 2. wave offsets per prefix, and the prefixes' starts in the segment
+        //    (thread t scans prefixes [t * per, (t + 1) * per), per <= 8)
+        uint32_t tot[8];
+        uint32_t run = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < 8; k++) {
+            const uint32_t q = t * per + k;
+            tot[k] = 0;
+            if (k < per && q < nq) {
+                const uint32_t c0 = cnt[q], c1 = cnt[nq + q], c2 = cnt[2 * nq + q], c3 = cnt[3 * nq + q];
+                cnt[q] = 0;
+                cnt[nq + q] = (uint16_t)c0;
+                cnt[2 * nq + q] = (uint16_t)(c0 + c1);
+                cnt[3 * nq + q] = (uint16_t)(c0 + c1 + c2);
+                tot[k] = c0 + c1 + c2 + c3;
+                run += tot[k];
+            }
+        }
+        uint32_t total;
+        uint32_t st = block256_exscan(run, wsum, total);
+#pragma unroll
+        for (uint32_t k = 0; k < 8; k++) {
+            const uint32_t q = t * per + k;
+            if (k < per && q < nq) {
+                sstart[q] = st;
+                st += tot[k];
+            }
+        }
+        __syncthreads();
+        // 3. stage in prefix order
+#pragma unroll
+        for (uint32_t j = 0; j < kPsPer; j++) {
+            const bool ok = q0 + j * 64 + lane < seg + len;
+            if (ok) {
+                const uint32_t q = (a[j] >> shift) & (nq - 1);
+                stage[sstart[q] + cnt[w * nq + q] + rk[j]] = (E)a[j];
+            }
+        }
+        __syncthreads();
+        // 4. write out in runs
+        for (uint32_t p = t; p < len; p += 256) {
+            const uint32_t x = (uint32_t)stage[p];
+            const uint32_t q = (x >> shift) & (nq - 1);
+            out[cursor[q] + (p - sstart[q])] = (E)x;
+        }
+        __syncthreads();
+        // 5. cursors past the segment, counts cleared
+        for (uint32_t q = t; q < nq; q += 256) {
+            const uint32_t end = (q + 1 < nq) ? sstart[q + 1] : len;
+            cursor[q] += end - sstart[q];
+            cnt[q] = cnt[nq + q] = cnt[2 * nq + q] = cnt[3 * nq + q] = 0;
+        }
+        __syncthreads();
     }
 }
 
@@ -283,7 +397,9 @@ template <typename E>
 static hipError_t launch_ps_t(const PsDesc &d, const LaunchCtx &ctx)
 {
     const uint32_t L = d.L;
-    hipLaunchKernelGGL(k_ps_hist<E>, dim3(d.P), dim3(256), (1u << L) * 4, ctx.stream, d);
+    const uint32_t copies = (1u << L) <= 512 ? 8u : (4096u >> L);
+    hipLaunchKernelGGL(k_ps_hist<E>, dim3(d.P), dim3(256), (1u << L) * copies * 4, ctx.stream, d,
+                       ((uintptr_t)d.text & 15) == 0);
     const uint32_t bits_blocks = (uint32_t)std::min<uint64_t>(2048, std::max<uint64_t>(1, blocks_of(d.W * 64, 256)));
     uint32_t *cur = d.H0, *nxt = d.H1;
     if (L >= 2) {
@@ -300,8 +416,9 @@ static hipError_t launch_ps_t(const PsDesc &d, const LaunchCtx &ctx)
         hipLaunchKernelGGL(k_ps_scan_up, dim3(nb), dim3(1024), 0, ctx.stream, cur, d.bsum, l, d.P, d.kind);
         hipLaunchKernelGGL(k_ps_scan_top, dim3(1), dim3(1024), 0, ctx.stream, d.bsum, nb);
         hipLaunchKernelGGL(k_ps_scan_down, dim3(nb), dim3(1024), 0, ctx.stream, cur, d.bsum, l, d.P, d.kind);
-        hipLaunchKernelGGL(k_ps_sort<E>, dim3(blocks_of(d.P, 4)), dim3(256), 4u * (1u << l) * 4, ctx.stream, d, l,
-                           cur);
+        // cursors and starts (u32), wave counts (u16), the staged segment
+        const uint32_t lds = (1u << l) * 16 + kPsSeg * (uint32_t)sizeof(E);
+        hipLaunchKernelGGL(k_ps_sort<E>, dim3(d.P), dim3(256), lds, ctx.stream, d, l, cur);
         hipLaunchKernelGGL(k_ps_bits<E>, dim3(bits_blocks), dim3(256), 0, ctx.stream, (const void *)d.sorted, d.n,
                            L, l, d.bits + (uint64_t)l * d.W, d.W, d.zeros + l, true);
         std::swap(cur, nxt);
