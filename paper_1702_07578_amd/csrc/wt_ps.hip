@@ -245,9 +245,11 @@ __global__ __launch_bounds__(256) void k_ps_sort(PsDesc d, uint32_t l, const uin
             const uint32_t q = (a[j] >> shift) & (nq - 1);
             uint64_t peers = __ballot(ok);
             for (uint32_t k = 0; k < l; k++) {
-                const bool bit = (q >> k) & 1u;
-                const uint64_t m = __ballot(bit);
-                peers &= bit ? m : ~m;
+                // inv: all ones when bit k of q is clear; the lanes that agree
+                // with this one on bit k are the ballot, flipped by inv
+                const int32_t inv = __builtin_amdgcn_sbfe((int32_t)~q, k, 1);
+                const uint64_t m = __ballot(inv == 0);
+                peers &= m ^ ((uint64_t)(uint32_t)inv << 32 | (uint32_t)inv);
             }
             const uint32_t rank = (uint32_t)__popcll(peers & lt);
             const uint32_t num = (uint32_t)__popcll(peers);
