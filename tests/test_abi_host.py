@@ -103,3 +103,20 @@ def test_export_sizes_and_refusals():
     assert B.wt_export_nodes(ctypes.byref(v), fake, fake, 100, fake, ws, None) == B.WT_ENOSPACE
     assert B.wt_export_nodes(ctypes.byref(v), fake, fake, 1 << 12, fake, ws - 1, None) == B.WT_ENOSPACE
     assert B.wt_export_nodes(ctypes.byref(v), None, fake, 1 << 12, fake, ws, None) == B.WT_EINVAL
+
+
+def test_sorting_build_sizes_and_refusals():
+    """Workspace of the sorting build and its host-side refusals."""
+    from paper_1702_07578_amd import binding as B
+    assert B.wt_ps_workspace_bytes(1 << 20, 1, 7) >= (1 << 20)  # the sorted copy
+    assert B.wt_ps_workspace_bytes(1 << 20, 4, 12) >= 4 << 20
+    assert B.wt_ps_workspace_bytes(1 << 20, 2, 13) == 0
+    assert B.wt_ps_workspace_bytes(1 << 20, 3, 8) == 0
+    v = B.WtLevels()
+    fake = ctypes.c_void_p(1 << 20)
+    assert B.wt_levels_bind(ctypes.byref(v), fake, B.wt_output_bytes(1000, 8), 1000, 8, 0) == B.WT_OK
+    need = B.wt_ps_workspace_bytes(1000, 1, 8)
+    assert B.wt_ps_build(0, fake, 1000, 1, 8, ctypes.byref(v), fake, need - 1, None) == B.WT_ENOSPACE
+    assert B.wt_ps_build(1, fake, 1000, 1, 8, ctypes.byref(v), fake, need, None) == B.WT_EINVAL  # kind mismatch
+    assert B.wt_ps_build(0, ctypes.c_void_p((1 << 20) + 1), 1000, 2, 8, ctypes.byref(v), fake, need,
+                         None) == B.WT_EINVAL  # misaligned u16 text
