@@ -205,6 +205,101 @@ __device__ inline uint32_t block256_exscan(uint32_t v, uint32_t *wsum, uint32_t 
     return before + inc - v;
 }
 
+// one segment; FULL: all kPsSeg symbols present (no bounds tests)
+template <typename E, bool FULL>
+__device__ inline void ps_segment(const E *__restrict__ src, E *__restrict__ out, uint32_t len, uint32_t l,
+                                  uint32_t shift, uint32_t *cursor, uint32_t *sstart, uint16_t *cnt, E *stage,
+                                  uint32_t *wsum)
+{
+    const uint32_t nq = 1u << l;
+    const uint32_t t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const uint32_t per = (nq + 255) / 256;
+    uint16_t *mycnt = cnt + w * nq;
+    // 1. ranks within the wave's quarter
+    uint32_t a[kPsPer], rk[kPsPer];
+    const uint32_t base0 = w * (kPsSeg / 4) + lane;
+#pragma unroll
+    for (uint32_t j = 0; j < kPsPer; j++) {
+        const uint32_t o = base0 + j * 64;
+        a[j] = (FULL || o < len) ? (uint32_t)src[o] : 0u;
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < kPsPer; j++) {
+        const bool ok = FULL || base0 + j * 64 < len;
+        const uint32_t q = (a[j] >> shift) & (nq - 1);
+        uint64_t peers = FULL ? ~0ull : __ballot(ok);
+        for (uint32_t k = 0; k < l; k++) {
+            // inv: all ones when bit k of q is clear; the lanes that agree
+            // with this one on bit k are the ballot, flipped by inv
+            const int32_t inv = __builtin_amdgcn_sbfe((int32_t)~q, k, 1);
+            const uint64_t m = __ballot(inv == 0);
+            peers &= m ^ ((uint64_t)(uint32_t)inv << 32 | (uint32_t)inv);
+        }
+        const uint32_t rank = mbcnt64(peers);
+        const uint32_t num = (uint32_t)__popcll(peers);
+        rk[j] = 0;
+        if (ok) {
+            const uint32_t base = mycnt[q];
+            rk[j] = base + rank;
+            if (rank + 1 == num) mycnt[q] = (uint16_t)(base + num);  // the last lane of the prefix
+        }
+    }
+    __syncthreads();
+    // 2. wave offsets per prefix, and the prefixes' starts in the segment
+    //    (thread t scans prefixes [t * per, (t + 1) * per), per <= 8)
+    uint32_t tot[8];
+    uint32_t run = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < 8; k++) {
+        const uint32_t q = t * per + k;
+        tot[k] = 0;
+        if (k < per && q < nq) {
+            const uint32_t c0 = cnt[q], c1 = cnt[nq + q], c2 = cnt[2 * nq + q], c3 = cnt[3 * nq + q];
+            cnt[q] = 0;
+            cnt[nq + q] = (uint16_t)c0;
+            cnt[2 * nq + q] = (uint16_t)(c0 + c1);
+            cnt[3 * nq + q] = (uint16_t)(c0 + c1 + c2);
+            tot[k] = c0 + c1 + c2 + c3;
+            run += tot[k];
+        }
+    }
+    uint32_t total;
+    uint32_t st = block256_exscan(run, wsum, total);
+#pragma unroll
+    for (uint32_t k = 0; k < 8; k++) {
+        const uint32_t q = t * per + k;
+        if (k < per && q < nq) {
+            sstart[q] = st;
+            st += tot[k];
+        }
+    }
+    __syncthreads();
+    // 3. stage in prefix order
+#pragma unroll
+    for (uint32_t j = 0; j < kPsPer; j++) {
+        if (FULL || base0 + j * 64 < len) {
+            const uint32_t q = (a[j] >> shift) & (nq - 1);
+            stage[sstart[q] + cnt[w * nq + q] + rk[j]] = (E)a[j];
+        }
+    }
+    __syncthreads();
+    // 4. write out in runs
+#pragma unroll 4
+    for (uint32_t p = t; p < (FULL ? kPsSeg : len); p += 256) {
+        const uint32_t x = (uint32_t)stage[p];
+        const uint32_t q = (x >> shift) & (nq - 1);
+        out[cursor[q] + (p - sstart[q])] = (E)x;
+    }
+    __syncthreads();
+    // 5. cursors past the segment, counts cleared
+    for (uint32_t q = t; q < nq; q += 256) {
+        const uint32_t end = (q + 1 < nq) ? sstart[q + 1] : len;
+        cursor[q] += end - sstart[q];
+        cnt[q] = cnt[nq + q] = cnt[2 * nq + q] = cnt[3 * nq + q] = 0;
+    }
+    __syncthreads();
+}
+
 template <typename E>
 __global__ __launch_bounds__(256) void k_ps_sort(PsDesc d, uint32_t l, const uint32_t *__restrict__ B)
 {
@@ -215,7 +310,7 @@ __global__ __launch_bounds__(256) void k_ps_sort(PsDesc d, uint32_t l, const uin
     uint32_t *sstart = cursor + nq;    // [nq]: start of q in the staged segment
     uint16_t *cnt = (uint16_t *)(sstart + nq);  // [4][nq]: per wave counts, then offsets
     E *stage = (E *)(sm + 4 * nq);     // [kPsSeg], 16-byte aligned
-    const uint32_t t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const uint32_t t = threadIdx.x;
     const uint32_t c = blockIdx.x;
     for (uint32_t q = t; q < nq; q += 256) {
         cursor[q] = B[(uint64_t)q * d.P + c];
@@ -225,95 +320,14 @@ __global__ __launch_bounds__(256) void k_ps_sort(PsDesc d, uint32_t l, const uin
     const uint64_t i0 = (uint64_t)c * d.C;
     const uint64_t i1 = min(d.n, i0 + d.C);
     const uint32_t shift = d.L - l;
-    const uint64_t lt = (1ull << lane) - 1;
-    const uint32_t per = (nq + 255) / 256;  // prefixes per thread in the scan
     E *out = (E *)d.sorted;
-    uint16_t *mycnt = cnt + w * nq;
     for (uint64_t seg = i0; seg < i1; seg += kPsSeg) {
         const uint32_t len = (uint32_t)min<uint64_t>(kPsSeg, i1 - seg);
-        // 1. ranks within the wave's quarter
-        uint32_t a[kPsPer], rk[kPsPer];
-        const uint64_t q0 = seg + w * (kPsSeg / 4);
-#pragma unroll
-        for (uint32_t j = 0; j < kPsPer; j++) {
-            const uint64_t i = q0 + j * 64 + lane;
-            a[j] = (i < seg + len) ? sym_load<E>(d.text, i) : 0u;
-        }
-#pragma unroll
-        for (uint32_t j = 0; j < kPsPer; j++) {
-            const bool ok = q0 + j * 64 + lane < seg + len;
-            const uint32_t q = (a[j] >> shift) & (nq - 1);
-            uint64_t peers = __ballot(ok);
-            for (uint32_t k = 0; k < l; k++) {
-                // inv: all ones when bit k of q is clear; the lanes that agree
-                // with this one on bit k are the ballot, flipped by inv
-                const int32_t inv = __builtin_amdgcn_sbfe((int32_t)~q, k, 1);
-                const uint64_t m = __ballot(inv == 0);
-                peers &= m ^ ((uint64_t)(uint32_t)inv << 32 | (uint32_t)inv);
-            }
-            const uint32_t rank = (uint32_t)__popcll(peers & lt);
-            const uint32_t num = (uint32_t)__popcll(peers);
-            rk[j] = 0;
-            if (ok) {
-                const uint32_t base = mycnt[q];
-                rk[j] = base + rank;
-                if (rank + 1 == num) mycnt[q] = (uint16_t)(base + num);
-            }
-        }
-        __syncthreads();
-        // 2. wave offsets per prefix, and the prefixes' starts in the segment
-        //    (thread t scans prefixes [t * per, (t + 1) * per), per <= 8)
-        uint32_t tot[8];
-        uint32_t run = 0;
-#pragma unroll
-        for (uint32_t k = 0; k < 8; k++) {
-            const uint32_t q = t * per + k;
-            tot[k] = 0;
-            if (k < per && q < nq) {
-                const uint32_t c0 = cnt[q], c1 = cnt[nq + q], c2 = cnt[2 * nq + q], c3 = cnt[3 * nq + q];
-                cnt[q] = 0;
-                cnt[nq + q] = (uint16_t)c0;
-                cnt[2 * nq + q] = (uint16_t)(c0 + c1);
-                cnt[3 * nq + q] = (uint16_t)(c0 + c1 + c2);
-                tot[k] = c0 + c1 + c2 + c3;
-                run += tot[k];
-            }
-        }
-        uint32_t total;
-        uint32_t st = block256_exscan(run, wsum, total);
-#pragma unroll
-        for (uint32_t k = 0; k < 8; k++) {
-            const uint32_t q = t * per + k;
-            if (k < per && q < nq) {
-                sstart[q] = st;
-                st += tot[k];
-            }
-        }
-        __syncthreads();
-        // 3. stage in prefix order
-#pragma unroll
-        for (uint32_t j = 0; j < kPsPer; j++) {
-            const bool ok = q0 + j * 64 + lane < seg + len;
-            if (ok) {
-                const uint32_t q = (a[j] >> shift) & (nq - 1);
-                stage[sstart[q] + cnt[w * nq + q] + rk[j]] = (E)a[j];
-            }
-        }
-        __syncthreads();
-        // 4. write out in runs
-        for (uint32_t p = t; p < len; p += 256) {
-            const uint32_t x = (uint32_t)stage[p];
-            const uint32_t q = (x >> shift) & (nq - 1);
-            out[cursor[q] + (p - sstart[q])] = (E)x;
-        }
-        __syncthreads();
-        // 5. cursors past the segment, counts cleared
-        for (uint32_t q = t; q < nq; q += 256) {
-            const uint32_t end = (q + 1 < nq) ? sstart[q + 1] : len;
-            cursor[q] += end - sstart[q];
-            cnt[q] = cnt[nq + q] = cnt[2 * nq + q] = cnt[3 * nq + q] = 0;
-        }
-        __syncthreads();
+        const E *src = (const E *)d.text + seg;
+        if (len == kPsSeg)
+            ps_segment<E, true>(src, out, len, l, shift, cursor, sstart, cnt, stage, wsum);
+        else
+            ps_segment<E, false>(src, out, len, l, shift, cursor, sstart, cnt, stage, wsum);
     }
 }
 
