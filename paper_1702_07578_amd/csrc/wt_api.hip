@@ -215,7 +215,7 @@ static int schedule(const std::vector<TextDesc> &ds, Sched &s)
         push(s.b_chunks, ac, d.nchunks);
         push(s.b_dir, adir, (uint64_t)d.L * d.dir_chunks);
         push(s.b_tmpdir, atmp, deep ? (uint64_t)(d.L - d.K) * d.dir_chunks : 0);
-        push(s.b_gather, aga, deep ? (uint64_t)(d.L - d.K) * d.W : 0);
+        push(s.b_gather, aga, deep ? (uint64_t)(d.L - d.K) * (d.W / kGatherWords) : 0);
         for (uint32_t st = 0; st < max_steps; st++) {
             const bool has = deep && (d.K + st + 1 < d.L);
             push(s.b_walk[st], aw[st], has ? (1ull << (d.K + st)) : 0);

@@ -379,7 +379,10 @@ __global__ __launch_bounds__(256) void k_walk(const TextDesc *__restrict__ descs
     nxt[2 * nn + 2 * p + 1] = wts + (h - ones);
 }
 
-// Gather: every word of WT level l >= K from the WM level's intervals.
+// Gather: every word of WT level l >= K from the WM level's intervals; one
+// thread fills kGatherWords consecutive words, keeping the interval of the
+// previous piece (the next piece is in the same interval or the next
+// non-empty one far more often than not), so most pieces need no search.
 __global__ __launch_bounds__(256) void k_gather(const TextDesc *__restrict__ descs,
                                                 const uint32_t *__restrict__ bases, uint32_t nd,
                                                 uint32_t nitems)
@@ -390,39 +393,51 @@ __global__ __launch_bounds__(256) void k_gather(const TextDesc *__restrict__ des
     const TextDesc &d = descs[ti];
     const uint64_t idx = item - item_base(bases, nd, ti);
     if (d.kind != WT_TREE || d.G <= 1) return;
-    const uint32_t l = d.K + (uint32_t)(idx / d.W);
-    const uint64_t w = idx % d.W;
+    const uint64_t Wg = d.W / kGatherWords;  // W is a multiple of 8
+    const uint32_t l = d.K + (uint32_t)(idx / Wg);
     if (l >= d.L) return;
+    const uint64_t w0 = (idx % Wg) * kGatherWords;
     uint64_t *out = d.bits + (uint64_t)l * d.W;
     const uint64_t *wm = d.tmp_bits + (uint64_t)(l - d.K) * d.W;
     const uint32_t np = 1u << l;
     const uint32_t *tab = d.walk + walk_off(d.K, l);
-    const uint64_t ws = w << 6;
-    const uint64_t we = min(ws + 64, d.n);
-    uint64_t val = 0;
-    uint64_t pos = ws;
-    while (pos < we) {
-        // largest p with wt_start[p] <= pos: the non-empty interval holding pos
-        uint32_t lo = 0, hi = np;
-        while (hi - lo > 1) {
-            uint32_t mid = (lo + hi) >> 1;
-            if (tab[2 * np + mid] <= pos) lo = mid;
-            else hi = mid;
+    uint32_t lo = np;  // interval of the previous piece (none yet)
+    for (uint32_t k = 0; k < kGatherWords; k++) {
+        const uint64_t ws = (w0 + k) << 6;
+        const uint64_t we = min(ws + 64, d.n);
+        uint64_t val = 0;
+        uint64_t pos = ws;
+        while (pos < we) {
+            // the non-empty interval holding pos: the previous one or the
+            // next one when they hold it, else the largest p with
+            // wt_start[p] <= pos (found by binary search)
+            if (lo < np && tab[2 * np + lo] <= pos && pos < (uint64_t)tab[2 * np + lo] + tab[np + lo]) {
+            } else if (lo + 1 < np && tab[2 * np + lo + 1] == pos && tab[np + lo + 1] != 0) {
+                lo = lo + 1;
+            } else {
+                lo = 0;
+                uint32_t hi = np;
+                while (hi - lo > 1) {
+                    uint32_t mid = (lo + hi) >> 1;
+                    if (tab[2 * np + mid] <= pos) lo = mid;
+                    else hi = mid;
+                }
+            }
+            const uint64_t ts = tab[2 * np + lo], hh = tab[np + lo], ms = tab[lo];
+            uint64_t end = ts + hh;
+            if (end > we) end = we;
+            if (end <= pos) break;  // cannot happen for consistent tables
+            const uint32_t cnt = (uint32_t)(end - pos);
+            const uint64_t s = ms + (pos - ts);
+            const uint32_t sh = (uint32_t)(s & 63);
+            uint64_t x = wm[s >> 6] >> sh;
+            if (sh && sh + cnt > 64) x |= wm[(s >> 6) + 1] << (64 - sh);
+            if (cnt < 64) x &= (1ull << cnt) - 1;
+            val |= x << (pos - ws);
+            pos = end;
         }
-        const uint64_t ts = tab[2 * np + lo], hh = tab[np + lo], ms = tab[lo];
-        uint64_t end = ts + hh;
-        if (end > we) end = we;
-        if (end <= pos) break;  // cannot happen for consistent tables
-        const uint32_t cnt = (uint32_t)(end - pos);
-        const uint64_t s = ms + (pos - ts);
-        const uint32_t sh = (uint32_t)(s & 63);
-        uint64_t x = wm[s >> 6] >> sh;
-        if (sh && sh + cnt > 64) x |= wm[(s >> 6) + 1] << (64 - sh);
-        if (cnt < 64) x &= (1ull << cnt) - 1;
-        val |= x << (pos - ws);
-        pos = end;
+        out[w0 + k] = val;
     }
-    out[w] = val;
 }
 
 // ---------------------------------------------------------------------------

@@ -113,16 +113,24 @@ __global__ __launch_bounds__(256) void k_cgather(wt_levels src, wt_levels dst, c
     const uint64_t we = min(ws0 + 64, n);
     uint64_t val = 0;
     uint64_t pos = ws0;
+    uint32_t lo = np;  // rank (in dst order) of the previous piece's interval
     while (pos < we) {
         // the last interval (in dst order) starting at or before pos; an
         // empty interval shares its start with the next one, so it is never
-        // the last such interval
-        uint32_t lo = 0, hi = np;
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            const uint32_t p = to_wt ? mid : rev_bits(mid, l);
-            if ((to_wt ? ws[p] : ms[p]) <= pos) lo = mid;
-            else hi = mid;
+        // the last such interval.  The next interval in dst order is taken
+        // directly when it starts at pos and is not empty.
+        const uint32_t pn = to_wt ? lo + 1 : rev_bits(lo + 1, l);
+        if (lo + 1 < np && (to_wt ? ws[pn] : ms[pn]) == pos && len[pn] != 0) {
+            lo = lo + 1;
+        } else {
+            lo = 0;
+            uint32_t hi = np;
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                const uint32_t p = to_wt ? mid : rev_bits(mid, l);
+                if ((to_wt ? ws[p] : ms[p]) <= pos) lo = mid;
+                else hi = mid;
+            }
         }
         const uint32_t p = to_wt ? lo : rev_bits(lo, l);
         const uint64_t ds = to_wt ? ws[p] : ms[p];
@@ -296,16 +304,31 @@ __global__ __launch_bounds__(256) void k_mgather(const wt_levels *__restrict__ p
     const uint64_t we = min(b0 + 64, dst.n);
     uint64_t val = 0;
     uint64_t pos = b0;
+    uint64_t lo = ne;  // position (in the whole's order) of the previous piece's interval
     while (pos < we) {
         // the last (prefix, piece) interval, in the whole's order, starting
-        // at or before pos (never an empty one: it shares the next start)
-        uint64_t lo = 0, hi = ne;
-        while (hi - lo > 1) {
-            const uint64_t mid = (lo + hi) >> 1;
-            const uint32_t k = (uint32_t)(mid / count), c = (uint32_t)(mid % count);
+        // at or before pos (never an empty one: it shares the next start);
+        // the next one in order is taken directly when it starts at pos and
+        // is not empty
+        bool next = false;
+        if (lo + 1 < ne) {
+            const uint32_t k = (uint32_t)((lo + 1) / count), c = (uint32_t)((lo + 1) % count);
             const uint32_t p = wt ? k : rev_bits(k, l);
-            if (ds[(uint64_t)p * count + c] <= pos) lo = mid;
-            else hi = mid;
+            next = ds[(uint64_t)p * count + c] == pos &&
+                   tabs[c * stride + ctab_off(l) + np + p] != 0;
+        }
+        if (next) {
+            lo = lo + 1;
+        } else {
+            lo = 0;
+            uint64_t hi = ne;
+            while (hi - lo > 1) {
+                const uint64_t mid = (lo + hi) >> 1;
+                const uint32_t k = (uint32_t)(mid / count), c = (uint32_t)(mid % count);
+                const uint32_t p = wt ? k : rev_bits(k, l);
+                if (ds[(uint64_t)p * count + c] <= pos) lo = mid;
+                else hi = mid;
+            }
         }
         const uint32_t k = (uint32_t)(lo / count), c = (uint32_t)(lo % count);
         const uint32_t p = wt ? k : rev_bits(k, l);

@@ -25,6 +25,7 @@ constexpr uint32_t kMaxGroupBits = 8;
 constexpr uint32_t kTargetRanges = 12288;
 // Ranges per chunk of the column scans over the range histograms.
 constexpr uint32_t kBorderChunk = 32;
+constexpr uint32_t kGatherWords = 1;  // words per thread of the WT gather (divides W, a multiple of 8)
 // Directory: 512-bit blocks, chunks of kDirChunk blocks per workgroup.
 constexpr uint32_t kDirChunk = 1024;
 
