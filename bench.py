@@ -38,6 +38,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+WORKLOAD_TEXT = {
+    "markov96": "order-2 Markov text, sigma=96",
+    "markov4": "order-2 Markov text, sigma=4",
+    "uniform256": "i.i.d. uniform, sigma=256",
+    "uniform16": "i.i.d. uniform, sigma=2^16",
+    "zipf20": "Zipf(1.1) over 2^20 permuted ids",
+}
+
+
 def scatter_traffic(per_launch_alg_bytes):
     """HBM bytes per scatter launch from the committed counter runs, or None
     when there are none or the kernel source changed since they were taken."""
@@ -401,12 +410,15 @@ def main():
     scat = kernels.get("scatter", {"avg_ms": float("nan"), "launches": 0})
     per_launch_bytes = (n * b + L * W * 8) / max(1, G)
     achieved = per_launch_bytes / (scat["avg_ms"] / 1e3) / 1e9
+    default_markov = args.workload == "markov96" and not args.n
     roofline = {"kernel": "scatter", "bound": "hbm",
-                "limiter": "vector-instruction issue: about 83 VALU instructions per 64 symbols "
-                           "for 7 levels (rocprofv3 SQ_INSTS_VALU), about 76% of the chip's issue rate",
+                "limiter": ("vector-instruction issue: about 83 VALU instructions per 64 symbols "
+                            "for 7 levels (rocprofv3 SQ_INSTS_VALU), about 76% of the chip's issue rate"
+                            if default_markov else
+                            "vector-instruction issue (counters taken on markov96 only)"),
                 "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": scatter_traffic(per_launch_bytes),
+                "traffic": scatter_traffic(per_launch_bytes) if default_markov else None,
                 "alg_bytes_per_launch": int(per_launch_bytes), "avg_launch_ms": round(scat["avg_ms"], 4)}
     # whole-build roofline: B_alg = 2 n b + L W 8 + directories, per build
     nb = W // 8
@@ -501,7 +513,8 @@ def main():
     # the second build strategy (a counting sort of the text per level): its
     # time per build, and equality with the default build
     ps_ms = {}
-    for k, name in ((B.WT_TREE, "sort_build_wt_ms"), (B.WT_MATRIX, "sort_build_wm_ms")):
+    for k, name in (((B.WT_TREE, "sort_build_wt_ms"), (B.WT_MATRIX, "sort_build_wm_ms"))
+                    if B.wt_ps_workspace_bytes(n, b, L) else ()):
         ps_out = B.Structure(n, L, k, device=dev)
         ps_ws = torch.empty(int(B.wt_ps_workspace_bytes(n, b, L)), dtype=torch.uint8, device=dev)
         _, t_ms = timed(lambda: B.ps_build(d_text, n, b, L, k, ws=ps_ws, out=ps_out))
@@ -532,10 +545,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u8",
+        "dtype": f"u{8 * b}",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: order-2 Markov text, n={n} uint8 symbols, sigma=96, "
-                               f"{L} levels; step = WT build + WM build (levels, Z, rank/select directories)",
+        "config": {"workload": f"{args.workload}: {WORKLOAD_TEXT.get(args.workload, 'text')}, n={n} "
+                               f"uint{8 * b} symbols, {L} levels; step = WT build + WM build (levels, Z, "
+                               f"rank/select directories)",
                    "n": n, "sym_bytes": b, "lg_sigma": L, "tile_log2": args.tile_log2 or "auto",
                    "group_bits": args.group_bits or "auto"},
         "roofline": roofline,

@@ -51,7 +51,7 @@ struct WaveSmem {
     uint32_t GK[REORDER ? kKeys : 1];
     uint16_t hK[REORDER ? kKeys : 1];
     uint16_t loK[REORDER ? kKeys : 1];
-    union {
+    union alignas(16) {
         E elem[kWaveTile];  // the tile, in its next order (loading and splits)
         struct {            // copy-out, after the splits
             uint16_t kw[kMaxWords];  // run of every full word
@@ -332,10 +332,32 @@ __device__ __attribute__((always_inline)) inline void split_pass(uint32_t (&v)[k
 
 // One tile of kWaveTile symbols (the text's last tile may be shorter; it is
 // padded).
+// 16-byte units of a whole tile per lane, and the tile's units as loaded by
+// the wave (lane-interleaved: unit u * 64 + lane)
+template <typename E>
+struct TileUnits {
+    static constexpr uint32_t kPerLane = kWaveTile * sizeof(E) / 16 / 64;
+    uint4 q[kPerLane];
+    __device__ void load(const E *tile)
+    {
+        const uint4 *u = (const uint4 *)tile;
+        const uint32_t lane = lane_id();
+#pragma unroll
+        for (uint32_t i = 0; i < kPerLane; i++) q[i] = u[i * 64 + lane];
+    }
+};
+
+// Tiles whose units are loaded one tile ahead (16-byte text, symbols of one
+// byte): while a tile is split, the next one is on its way.
+template <typename E>
+constexpr bool kPrefetch = sizeof(E) == 1;
+
 template <typename E, bool REORDER>
 __device__ __attribute__((always_inline)) inline void wave_tile(const TextDesc &d, uint32_t g,
                                                                 uint32_t Kg, uint32_t t,
-                                                                WaveSmem<E, REORDER> &sm)
+                                                                WaveSmem<E, REORDER> &sm,
+                                                                TileUnits<E> &tu, bool vec,
+                                                                bool have, uint32_t t1)
 {
     const uint32_t lane = lane_id();
     const uint64_t start = (uint64_t)t * kWaveTile;
@@ -352,7 +374,32 @@ __device__ __attribute__((always_inline)) inline void wave_tile(const TextDesc &
     //    the tables are built)
     for (uint32_t k = lane; k < nk; k += 64) cnt[k] = 0;
     wave_sync();
-    {
+    if (!padded && vec) {
+        // whole tile of a 16-byte aligned sequence: 16-byte units; with
+        // prefetch they were loaded during the previous tile
+        if (!kPrefetch<E> || !have) tu.load((const E *)seq_in(d, g) + start);
+        uint4 *eu = (uint4 *)sm.elem;
+#pragma unroll
+        for (uint32_t i = 0; i < TileUnits<E>::kPerLane; i++) eu[i * 64 + lane] = tu.q[i];
+        // the key's bits that lie inside the symbol (the rest are zero)
+        constexpr uint32_t width = 8 * sizeof(E);
+        const uint32_t kw = shift >= width ? 0u : min(Kg, width - shift);
+        const uint32_t ks = shift >= width ? 0u : shift;
+#pragma unroll
+        for (uint32_t i = 0; i < TileUnits<E>::kPerLane; i++) {
+            const uint32_t w4[4] = {tu.q[i].x, tu.q[i].y, tu.q[i].z, tu.q[i].w};
+#pragma unroll
+            for (uint32_t j = 0; j < 4; j++)
+#pragma unroll
+                for (uint32_t s = 0; s < 4 / sizeof(E); s++)
+                    atomicAdd(&cnt[__builtin_amdgcn_ubfe(w4[j], s * width + ks, kw)], 1u);
+        }
+        if (kPrefetch<E>) {
+            // the next tile of the range, when it is whole
+            const uint64_t nstart = start + kWaveTile;
+            if (t + 1 < t1 && nstart + kWaveTile <= d.n) tu.load((const E *)seq_in(d, g) + nstart);
+        }
+    } else {
         uint32_t v[kChunks];
         if (!padded) {
 #pragma unroll
@@ -458,7 +505,10 @@ __device__ void wave_range(const TextDesc &d, uint32_t g, uint32_t Kg, uint32_t 
     for (uint32_t e = lane; e < kRuns; e += 64) sm.pend[e] = kNoPend;
     wave_sync();
     const uint32_t t0 = r * d.R, t1 = min(d.ntiles, t0 + d.R);
-    for (uint32_t t = t0; t < t1; t++) wave_tile(d, g, Kg, t, sm);
+    const E *seq = (const E *)seq_in(d, g);
+    const bool vec = ((uintptr_t)seq & 15) == 0;
+    TileUnits<E> tu;
+    for (uint32_t t = t0; t < t1; t++) wave_tile(d, g, Kg, t, sm, tu, vec, t > t0, t1);
     // words still open at the end of the range are shared with the next one
     for (uint32_t e = lane; e < lvl_off(Kg); e += 64) {
         if (sm.pend[e] == kNoPend) continue;
