@@ -412,8 +412,8 @@ def main():
     achieved = per_launch_bytes / (scat["avg_ms"] / 1e3) / 1e9
     default_markov = args.workload == "markov96" and not args.n
     roofline = {"kernel": "scatter", "bound": "hbm",
-                "limiter": ("vector-instruction issue: about 83 VALU instructions per 64 symbols "
-                            "for 7 levels (rocprofv3 SQ_INSTS_VALU), about 76% of the chip's issue rate"
+                "limiter": ("vector-instruction issue: about 79 VALU instructions per 64 symbols "
+                            "for 7 levels (rocprofv3 SQ_INSTS_VALU), about 78% of the chip's issue rate"
                             if default_markov else
                             "vector-instruction issue (counters taken on markov96 only)"),
                 "achieved": round(achieved, 1),
