@@ -218,6 +218,22 @@ int wt_merge(const wt_levels *parts, uint32_t count, wt_levels *dst, void *d_ws,
              hipStream_t stream);
 
 /*
+ * Both structures of one text (Section 5.1: the WT and the WM hold the same
+ * intervals of every level, in prefix order and in bit-reversed prefix
+ * order).  With lg_sigma <= 8 (one group of levels) the WT's build writes the
+ * WM as well: the tiles are split once, and every run of a level is copied
+ * to its WT interval and to its WM interval; the histogram and border passes
+ * are shared.  With more levels the two structures are built one after the
+ * other.  wt (kind WT_TREE) and wm (kind WT_MATRIX) are bound for (n,
+ * lg_sigma); both receive exactly what wt_build and wm_build write (levels,
+ * Z, directories, status).  Workspace: wt_pair_workspace_bytes(n, sym_bytes,
+ * lg_sigma).  Asynchronous on `stream`; argument errors as for wt_build_tuned.
+ */
+size_t wt_pair_workspace_bytes(uint64_t n, uint32_t sym_bytes, uint32_t lg_sigma);
+int wt_pair_build(const void *d_text, uint64_t n, uint32_t sym_bytes, uint32_t lg_sigma, wt_levels *wt,
+                  wt_levels *wm, void *d_ws, size_t ws_bytes, hipStream_t stream);
+
+/*
  * Construction by sorting (Section 3.2, construction using sorting,
  * Algorithm 2; the WM version of Section 5.1): the second build strategy,
  * with the same result as wt_build_tuned (levels, Z, directories, status).

@@ -255,11 +255,12 @@ struct DevBases {
 };
 
 static hipError_t run_build(const TextDesc *d_descs, const Sched &s, const DevBases &b,
-                            uint32_t grid_cap, const LaunchCtx &ctx)
+                            uint32_t grid_cap, const LaunchCtx &ctx, bool pair = false)
 {
     hipError_t e;
     for (uint32_t g = 0; g < s.gmax; g++) {
         GroupLaunch gl;
+        gl.pair = pair;
         gl.g = g;
         gl.nd = s.nd;
         gl.range_bases = b.ranges;
@@ -313,6 +314,62 @@ static int build_one(wt_kind kind, const void *d_text, uint64_t n, uint32_t sym_
     const uint32_t cap = tune ? tune->persist : 0;
     if (run_build(d_desc, s, b, cap, ctx) != hipSuccess) return WT_EHIP;
     return WT_OK;
+}
+
+// Both structures of one text.  With one group, the WT's build also writes
+// the WM from the same tile splits (the two differ only in where each run of
+// a level goes: prefix order or bit-reversed order, Section 5.1); with more
+// groups, the two are built one after the other.
+static int pair_one(const void *d_text, uint64_t n, uint32_t b, uint32_t L, wt_levels *wt,
+                    wt_levels *wm, void *d_ws, size_t ws_bytes, const LaunchCtx &ctx)
+{
+    WsPlan p;
+    int rc = plan_text(n, b, L, WT_TREE, nullptr, p);
+    if (rc != WT_OK) return rc;
+    if ((rc = check_out(wt, n, L, WT_TREE)) != WT_OK) return rc;
+    if ((rc = check_out(wm, n, L, WT_MATRIX)) != WT_OK) return rc;
+    if (n > 0 && !d_text) return WT_EINVAL;
+    if ((uintptr_t)d_text % b) return WT_EINVAL;
+    if (!d_ws) return WT_EINVAL;
+    if (p.d.G != 1 || L == 0) {
+        if ((rc = build_one(WT_TREE, d_text, n, b, L, wt, d_ws, ws_bytes, nullptr, ctx)) != WT_OK) return rc;
+        return build_one(WT_MATRIX, d_text, n, b, L, wm, d_ws, ws_bytes, nullptr, ctx);
+    }
+    const uint64_t dsz = align_up(sizeof(TextDesc), 256);
+    if (ws_bytes < p.bytes + 2 * dsz + 256) return WT_ENOSPACE;
+    uint8_t *base = (uint8_t *)align_up((uintptr_t)d_ws, 256);
+    TextDesc *d_desc = (TextDesc *)base, *d_desc2 = (TextDesc *)(base + dsz);
+    bind_ws(p, base + 2 * dsz);
+    p.d.text = d_text;
+    bind_out(p.d, *wt);
+    TextDesc d2 = p.d;  // the WM, for its directories
+    d2.kind = WT_MATRIX;
+    bind_out(d2, *wm);
+    p.d.pair = 1;
+    p.d.bits2 = wm->bits;
+    p.d.zeros2 = wm->zeros;
+    p.d.status2 = wm->status;
+    std::vector<TextDesc> ds{p.d};
+    Sched s;
+    if ((rc = schedule(ds, s)) != WT_OK) return rc;
+    if (launch_init(d2, d_desc2, ctx) != hipSuccess) return WT_EHIP;
+    if (launch_init(p.d, d_desc, ctx) != hipSuccess) return WT_EHIP;
+    DevBases bb;
+    bb.walk.assign(s.walk_items.size(), nullptr);
+    if (run_build(d_desc, s, bb, 0, ctx, true) != hipSuccess) return WT_EHIP;
+    if (launch_dirs(d_desc2, nullptr, 1, s.dir_items, s.max_levels, false, 0, ctx) != hipSuccess)
+        return WT_EHIP;
+    return WT_OK;
+}
+
+static size_t pair_ws_bytes(uint64_t n, uint32_t b, uint32_t L)
+{
+    WsPlan p;
+    if (plan_text(n, b, L, WT_TREE, nullptr, p) != WT_OK) return 0;
+    if (p.d.G == 1 && L > 0) return p.bytes + 2 * align_up(sizeof(TextDesc), 256) + 256;
+    WsPlan q;
+    if (plan_text(n, b, L, WT_MATRIX, nullptr, q) != WT_OK) return 0;
+    return std::max(p.bytes, q.bytes) + align_up(sizeof(TextDesc), 256) + 256;
 }
 
 }  // namespace wtg
@@ -370,6 +427,18 @@ int wt_build_tuned(wt_kind kind, const void *d_text, uint64_t n, uint32_t sym_by
 {
     LaunchCtx ctx{stream, nullptr, nullptr};
     return build_one(kind, d_text, n, sym_bytes, lg_sigma, out, d_ws, ws_bytes, tune, ctx);
+}
+
+size_t wt_pair_workspace_bytes(uint64_t n, uint32_t sym_bytes, uint32_t lg_sigma)
+{
+    return pair_ws_bytes(n, sym_bytes, lg_sigma);
+}
+
+int wt_pair_build(const void *d_text, uint64_t n, uint32_t sym_bytes, uint32_t lg_sigma, wt_levels *wt,
+                  wt_levels *wm, void *d_ws, size_t ws_bytes, hipStream_t stream)
+{
+    LaunchCtx ctx{stream, nullptr, nullptr};
+    return pair_one(d_text, n, sym_bytes, lg_sigma, wt, wm, d_ws, ws_bytes, ctx);
 }
 
 int wt_build(const void *d_text, uint64_t n, uint32_t sym_bytes, uint32_t lg_sigma,

@@ -29,8 +29,12 @@ __global__ void k_init(TextDesc d, TextDesc *dst)
     if (threadIdx.x == 0) {
         *dst = d;
         *d.status = WT_OK;
+        if (d.pair) *d.status2 = WT_OK;
     }
-    for (uint32_t l = threadIdx.x; l < d.L; l += blockDim.x) d.zeros[l] = 0;
+    for (uint32_t l = threadIdx.x; l < d.L; l += blockDim.x) {
+        d.zeros[l] = 0;
+        if (d.pair) d.zeros2[l] = 0;
+    }
 }
 
 // batch: clear the status word and Z of every text
@@ -119,7 +123,10 @@ __device__ void hist_range(const TextDesc &d, uint32_t g, uint32_t Kg, uint32_t 
         if (check && (e >> d.L) != 0) bad = true;
         atomicAdd(&hist[((e >> shift) & mask) * kHistCopies], 1u);
     }
-    if (bad) atomicExch(d.status, (int32_t)WT_ERANGE);
+    if (bad) {
+        atomicExch(d.status, (int32_t)WT_ERANGE);
+        if (d.pair) atomicExch(d.status2, (int32_t)WT_ERANGE);
+    }
     __syncthreads();
     uint32_t *H = d.H + (uint64_t)r * nk;
     for (uint32_t k = tid; k < nk; k += kTileThreads) {
@@ -278,6 +285,7 @@ __global__ __launch_bounds__(kBorderThreads) void k_borders(const TextDesc *__re
                 uint64_t z = 0;
                 for (uint32_t kk = 0; kk < (2u << tid); kk += 2) z += tot[lvl_off(tid + 1) + kk];
                 d.zeros[g * d.K + tid] = z;
+                if (d.pair) d.zeros2[g * d.K + tid] = z;
             }
             // deep WT: intervals of the K-bit prefixes (level K) seed the walk
             if (d.kind == WT_TREE && d.G > 1 && g == 0) {
@@ -324,8 +332,13 @@ __global__ __launch_bounds__(kBorderThreads) void k_borders(const TextDesc *__re
             for (uint32_t e = lane; e < lvl_off(Kg); e += 64) {
                 const uint32_t a = 31 - __clz(e + 1), kk = e - lvl_off(a), sh = Kg - a;
                 const uint32_t *kb = use_prefix_order(d, g, a, Kg) ? kbid : kbpi;
-                const uint32_t gs = sw[(kk + 1) << sh] - sw[kk << sh] + kb[e];
+                const uint32_t raw = sw[(kk + 1) << sh] - sw[kk << sh];
+                const uint32_t gs = raw + kb[e];
                 if ((gs & 63) != 0 && (gs >> 6) < d.W) level_ptr(d, g, a)[gs >> 6] = 0;
+                if (d.pair) {  // the WM of the pair: bit-reversed order
+                    const uint32_t gs2 = raw + kbpi[e];
+                    if ((gs2 & 63) != 0 && (gs2 >> 6) < d.W) d.bits2[(uint64_t)a * d.W + (gs2 >> 6)] = 0;
+                }
             }
             if (r == 0) {
                 // padding words, and the word holding position n (its bits
@@ -333,6 +346,8 @@ __global__ __launch_bounds__(kBorderThreads) void k_borders(const TextDesc *__re
                 for (uint32_t a = 0; a < Kg; a++) {
                     uint64_t *out = level_ptr(d, g, a);
                     for (uint64_t wd = (d.n >> 6) + lane; wd < d.W; wd += 64) out[wd] = 0;
+                    if (d.pair)
+                        for (uint64_t wd = (d.n >> 6) + lane; wd < d.W; wd += 64) d.bits2[(uint64_t)a * d.W + wd] = 0;
                 }
             }
         }

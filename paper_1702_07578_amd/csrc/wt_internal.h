@@ -68,6 +68,12 @@ struct TextDesc {
     uint32_t *walk;        // WT only, G > 1: per level l in [K,L): 3 x 2^l u32
     uint16_t *dir_bc;      // [Lall][nb] ones per 512-bit block
     uint32_t *dir_cs;      // [Lall][dir_chunks] chunk sums -> prefixes
+    // pair build (a WT desc with one group): the WM of the same text is
+    // written as well, from the same splits, into these outputs
+    uint32_t pair;
+    uint64_t *bits2;
+    uint64_t *zeros2;
+    int32_t *status2;
 };
 
 // Construction by sorting (the second strategy): text cut into P chunks of C
@@ -146,6 +152,7 @@ struct GroupLaunch {
     uint32_t bmask;    // symbol widths present: bit 0 (1 byte), 1 (2 bytes), 2 (4 bytes)
     uint32_t rmask;    // bit 0: some text ends with group g; bit 1: some text goes on
     uint32_t grid_cap; // 0: one workgroup per item
+    bool pair = false; // the pair scatter (WT and WM of one text, one group)
 };
 
 hipError_t launch_init(const TextDesc &d, TextDesc *d_dst, const LaunchCtx &ctx);

@@ -37,16 +37,19 @@ constexpr uint8_t kNoPend = 0, kPend = 1, kPendForeign = 2;
 // One wave's LDS.  Tables of levels 0..Kg-1 are indexed lvl_off(a) + key.
 // REORDER (the group's symbols move on to the next group's sequence) adds
 // the tables of level Kg, the finest key.
-template <typename E, bool REORDER>
+template <typename E, bool REORDER, bool PAIR>
 struct WaveSmem {
     // level a of the tile in order a; while the tables are built (and at a
     // range start) it holds the finest key counts and their prefix sums
     uint64_t bits[kMaxGroupBits][kChunks];
     uint64_t pend_v[kRuns];  // bits so far of the word a key's run ends in
+    uint64_t pend_v2[PAIR ? kRuns : 1];  // the same for the pair's WM
     uint32_t G[kRuns];       // global start of the key's bits for this tile
+    uint32_t G2[PAIR ? kRuns : 1];       // the same in the pair's WM
     uint16_t h[kRuns];       // the tile's count of every key
     uint16_t lo[kRuns];      // start of the key in the tile order of its level
     uint8_t pend[kRuns];     // state of that word
+    uint8_t pend2[PAIR ? kRuns : 1];
     uint32_t lvw[kMaxGroupBits];  // word offset of level a from the group's base pointer
     uint32_t GK[REORDER ? kKeys : 1];
     uint16_t hK[REORDER ? kKeys : 1];
@@ -148,9 +151,9 @@ __device__ inline uint32_t group_level0(const TextDesc &d, uint32_t g)
 
 // G at the first tile of range r: the range prefix of every finest key merged
 // upward, plus the key bases of each level.
-template <typename E, bool REORDER>
+template <typename E, bool REORDER, bool PAIR>
 __device__ inline void wave_range_start(const TextDesc &d, uint32_t g, uint32_t Kg, uint32_t r,
-                                        WaveSmem<E, REORDER> &sm)
+                                        WaveSmem<E, REORDER, PAIR> &sm)
 {
     const uint32_t lane = lane_id();
     const uint32_t nk = 1u << Kg;
@@ -166,7 +169,11 @@ __device__ inline void wave_range_start(const TextDesc &d, uint32_t g, uint32_t 
     }
     for (uint32_t a = 0; a < Kg; a++) {
         const uint32_t *kb = (use_prefix_order(d, g, a, Kg) ? d.KBid : d.KBpi) + lvl_off(a);
-        for (uint32_t k = lane; k < (1u << a); k += 64) sm.G[lvl_off(a) + k] += kb[k];
+        for (uint32_t k = lane; k < (1u << a); k += 64) {
+            const uint32_t raw = sm.G[lvl_off(a) + k];
+            sm.G[lvl_off(a) + k] = raw + kb[k];
+            if (PAIR) sm.G2[lvl_off(a) + k] = raw + d.KBpi[lvl_off(a) + k];  // the WM: bit-reversed order
+        }
     }
     if (REORDER) {
         const uint32_t *kb = d.KBpi + lvl_off(Kg);
@@ -186,21 +193,31 @@ __device__ inline uint32_t full_words(uint32_t gs, uint32_t hh)
 // Words that a run of this tile covers completely, all levels at once, by
 // plain stores: the full words of all runs are numbered run by run, and the
 // lanes take consecutive words.
-template <typename E, bool REORDER>
-__device__ __attribute__((always_inline)) inline void copy_full_words(const TextDesc &d, uint32_t g,
-                                                                      uint32_t Kg,
-                                                                      WaveSmem<E, REORDER> &sm)
+// One output of the scatter: the global starts of the runs, the words kept
+// at run ends, and the base of the group's bit vectors.
+struct Side {
+    uint32_t *G;
+    uint8_t *pend;
+    uint64_t *pend_v;
+    uint64_t *base;
+};
+
+template <typename E, bool REORDER, bool PAIR>
+__device__ __attribute__((always_inline)) inline void copy_full_words(const TextDesc &d, uint32_t Kg,
+                                                                      WaveSmem<E, REORDER, PAIR> &sm,
+                                                                      const Side &sd)
 {
     const uint32_t lane = lane_id();
     const uint32_t nr = lvl_off(Kg);
+    const uint32_t *G = sd.G;
     const uint32_t total = wave_exscan_n<4>(
-        nr, [&](uint32_t e) { return full_words(sm.G[e], sm.h[e]); },
+        nr, [&](uint32_t e) { return full_words(G[e], sm.h[e]); },
         [&](uint32_t e, uint32_t x) { sm.co.wb[e] = (uint16_t)x; });
     // run of every word: the run whose first word it is, carried forward
     for (uint32_t q = lane; q < total; q += 64) sm.co.kw[q] = 0;
     wave_sync();
     for (uint32_t e = lane; e < nr; e += 64)
-        if (full_words(sm.G[e], sm.h[e]) != 0) sm.co.kw[sm.co.wb[e]] = (uint16_t)e;
+        if (full_words(G[e], sm.h[e]) != 0) sm.co.kw[sm.co.wb[e]] = (uint16_t)e;
     wave_sync();
     constexpr uint32_t PER = (kMaxWords + 63) / 64;
     uint32_t m = 0;
@@ -221,11 +238,11 @@ __device__ __attribute__((always_inline)) inline void copy_full_words(const Text
         }
     }
     wave_sync();
-    uint64_t *base = group_base(d, g);
+    uint64_t *base = sd.base;
     const uint32_t W = (uint32_t)d.W;
     for (uint32_t q = lane; q < total; q += 64) {
         const uint32_t e = sm.co.kw[q], a = level_of(e);
-        const uint32_t gs = sm.G[e];
+        const uint32_t gs = G[e];
         const uint32_t gw = ((gs + 63) >> 6) + (q - sm.co.wb[e]);
         if (gw < W) base[sm.lvw[a] + gw] = stream_bits(sm.bits[a], sm.lo[e] + ((gw << 6) - gs), 64);
     }
@@ -235,12 +252,12 @@ __device__ __attribute__((always_inline)) inline void copy_full_words(const Text
 // First and last word of every run (one lane per run, all levels): merged
 // with the word kept from earlier tiles of the range, stored when complete,
 // kept otherwise.
-template <typename E, bool REORDER>
-__device__ __attribute__((always_inline)) inline void run_end_words(const TextDesc &d, uint32_t g,
-                                                                    uint32_t Kg,
-                                                                    WaveSmem<E, REORDER> &sm)
+template <typename E, bool REORDER, bool PAIR>
+__device__ __attribute__((always_inline)) inline void run_end_words(const TextDesc &d, uint32_t Kg,
+                                                                    WaveSmem<E, REORDER, PAIR> &sm,
+                                                                    const Side &sd)
 {
-    uint64_t *base = group_base(d, g);
+    uint64_t *base = sd.base;
     const uint32_t W = (uint32_t)d.W;
     for (uint32_t e = lane_id(); e < lvl_off(Kg); e += 64) {
         const uint32_t hh = sm.h[e];
@@ -250,7 +267,7 @@ __device__ __attribute__((always_inline)) inline void run_end_words(const TextDe
         const uint64_t *src = sm.bits[a];
         const uint32_t ls = sm.lo[e];
         // positions are below n < 2^32; ge may equal n
-        const uint32_t gs = sm.G[e], ge = gs + hh;
+        const uint32_t gs = sd.G[e], ge = gs + hh;
         const uint32_t fw = gs >> 6, lw = (ge - 1) >> 6;
         const uint32_t off = gs & 63;
         uint8_t newp = kNoPend;
@@ -259,9 +276,9 @@ __device__ __attribute__((always_inline)) inline void run_end_words(const TextDe
             const uint32_t cnt = min(hh, 64u - off);  // bits of the run in word fw
             uint64_t val = stream_bits(src, ls, cnt) << off;
             bool lowok = off == 0;
-            const uint8_t pw = sm.pend[e];
+            const uint8_t pw = sd.pend[e];
             if (!lowok && pw != kNoPend) {  // the kept word is fw
-                val |= sm.pend_v[e];
+                val |= sd.pend_v[e];
                 lowok = pw == kPend;
             }
             if (off + cnt == 64) {
@@ -277,8 +294,8 @@ __device__ __attribute__((always_inline)) inline void run_end_words(const TextDe
             newp = kPend;
             newv = stream_bits(src, ls + ((lw << 6) - gs), ge & 63);
         }
-        sm.pend[e] = newp;
-        sm.pend_v[e] = newv;
+        sd.pend[e] = newp;
+        sd.pend_v[e] = newv;
     }
 }
 
@@ -289,10 +306,10 @@ __device__ __attribute__((always_inline)) inline void run_end_words(const TextDe
 // symbols whose bits are all one: they sort after every real symbol at every
 // level, so the real symbols keep their places and the padding fills the
 // end of every level's stream.
-template <typename E, bool REORDER, bool SPLIT>
+template <typename E, bool REORDER, bool PAIR, bool SPLIT>
 __device__ __attribute__((always_inline)) inline void split_pass(uint32_t (&v)[kChunks], uint32_t a,
                                                                  uint32_t bit, uint32_t base1,
-                                                                 WaveSmem<E, REORDER> &sm)
+                                                                 WaveSmem<E, REORDER, PAIR> &sm)
 {
     const uint32_t lane = lane_id();
     uint32_t neg_lane = 0u - lane;
@@ -352,10 +369,10 @@ struct TileUnits {
 template <typename E>
 constexpr bool kPrefetch = sizeof(E) == 1;
 
-template <typename E, bool REORDER>
+template <typename E, bool REORDER, bool PAIR>
 __device__ __attribute__((always_inline)) inline void wave_tile(const TextDesc &d, uint32_t g,
                                                                 uint32_t Kg, uint32_t t,
-                                                                WaveSmem<E, REORDER> &sm,
+                                                                WaveSmem<E, REORDER, PAIR> &sm,
                                                                 TileUnits<E> &tu, bool vec,
                                                                 bool have, uint32_t t1)
 {
@@ -461,7 +478,7 @@ __device__ __attribute__((always_inline)) inline void wave_tile(const TextDesc &
     for (uint32_t c = 0; c < kChunks; c++) v[c] = sm.elem[c * 64 + lane];
     wave_sync();
     for (uint32_t a = 0; a + 1 < Kg; a++) {
-        split_pass<E, REORDER, true>(v, a, 1u << (shift + Kg - 1 - a), sm.lo[lvl_off(a + 1) + 1], sm);
+        split_pass<E, REORDER, PAIR, true>(v, a, 1u << (shift + Kg - 1 - a), sm.lo[lvl_off(a + 1) + 1], sm);
         wave_sync();
 #pragma unroll
         for (uint32_t c = 0; c < kChunks; c++) v[c] = sm.elem[c * 64 + lane];
@@ -471,7 +488,7 @@ __device__ __attribute__((always_inline)) inline void wave_tile(const TextDesc &
         // the last split orders the tile by its reversed Kg-bit key: each
         // key's symbols, in text order, go to the key's place in the next
         // group's sequence (padding sorts last and is dropped)
-        split_pass<E, REORDER, true>(v, Kg - 1, 1u << shift, sm.loK[1], sm);
+        split_pass<E, REORDER, PAIR, true>(v, Kg - 1, 1u << shift, sm.loK[1], sm);
         wave_sync();
         E *gout = (E *)seq_out(d, g);
         for (uint32_t p = lane; p < len; p += 64) {
@@ -481,28 +498,42 @@ __device__ __attribute__((always_inline)) inline void wave_tile(const TextDesc &
             if (gi < d.n) gout[gi] = x;
         }
     } else {
-        split_pass<E, REORDER, false>(v, Kg - 1, 1u << shift, 0u, sm);
+        split_pass<E, REORDER, PAIR, false>(v, Kg - 1, 1u << shift, 0u, sm);
     }
     wave_sync();
 
-    // 5. every level's runs to their interval starts
-    copy_full_words(d, g, Kg, sm);
-    run_end_words(d, g, Kg, sm);
+    // 5. every level's runs to their interval starts (and, for the pair, to
+    //    the WM's)
+    const Side s1{sm.G, sm.pend, sm.pend_v, group_base(d, g)};
+    copy_full_words(d, Kg, sm, s1);
+    run_end_words(d, Kg, sm, s1);
+    if (PAIR) {
+        wave_sync();
+        const Side s2{sm.G2, sm.pend2, sm.pend_v2, d.bits2};
+        copy_full_words(d, Kg, sm, s2);
+        run_end_words(d, Kg, sm, s2);
+    }
     wave_sync();
     // the next tile's runs start where this tile's end
-    for (uint32_t e = lane; e < lvl_off(Kg); e += 64) sm.G[e] += sm.h[e];
+    for (uint32_t e = lane; e < lvl_off(Kg); e += 64) {
+        sm.G[e] += sm.h[e];
+        if (PAIR) sm.G2[e] += sm.h[e];
+    }
     if (REORDER)
         for (uint32_t k = lane; k < nk; k += 64) sm.GK[k] += sm.hK[k];
     wave_sync();
 }
 
-template <typename E, bool REORDER>
+template <typename E, bool REORDER, bool PAIR>
 __device__ void wave_range(const TextDesc &d, uint32_t g, uint32_t Kg, uint32_t r,
-                           WaveSmem<E, REORDER> &sm)
+                           WaveSmem<E, REORDER, PAIR> &sm)
 {
     const uint32_t lane = lane_id();
     wave_range_start(d, g, Kg, r, sm);
-    for (uint32_t e = lane; e < kRuns; e += 64) sm.pend[e] = kNoPend;
+    for (uint32_t e = lane; e < kRuns; e += 64) {
+        sm.pend[e] = kNoPend;
+        if (PAIR) sm.pend2[e] = kNoPend;
+    }
     wave_sync();
     const uint32_t t0 = r * d.R, t1 = min(d.ntiles, t0 + d.R);
     const E *seq = (const E *)seq_in(d, g);
@@ -511,11 +542,18 @@ __device__ void wave_range(const TextDesc &d, uint32_t g, uint32_t Kg, uint32_t 
     for (uint32_t t = t0; t < t1; t++) wave_tile(d, g, Kg, t, sm, tu, vec, t > t0, t1);
     // words still open at the end of the range are shared with the next one
     for (uint32_t e = lane; e < lvl_off(Kg); e += 64) {
-        if (sm.pend[e] == kNoPend) continue;
-        const uint32_t wd = sm.G[e] >> 6;
-        if (wd < (uint32_t)d.W)
-            atomicOr((unsigned long long *)&group_base(d, g)[sm.lvw[level_of(e)] + wd],
-                     (unsigned long long)sm.pend_v[e]);
+        if (sm.pend[e] != kNoPend) {
+            const uint32_t wd = sm.G[e] >> 6;
+            if (wd < (uint32_t)d.W)
+                atomicOr((unsigned long long *)&group_base(d, g)[sm.lvw[level_of(e)] + wd],
+                         (unsigned long long)sm.pend_v[e]);
+        }
+        if (PAIR && sm.pend2[e] != kNoPend) {
+            const uint32_t wd = sm.G2[e] >> 6;
+            if (wd < (uint32_t)d.W)
+                atomicOr((unsigned long long *)&d.bits2[sm.lvw[level_of(e)] + wd],
+                         (unsigned long long)sm.pend_v2[e]);
+        }
     }
     wave_sync();
 }
@@ -523,12 +561,12 @@ __device__ void wave_range(const TextDesc &d, uint32_t g, uint32_t Kg, uint32_t 
 // Work item = (text, range); wave w of workgroup b takes items
 // b * kScatWaves + w, then strides by the whole grid.  The REORDER variant
 // takes the texts whose symbols move on to another group after group g.
-template <typename E, bool REORDER>
+template <typename E, bool REORDER, bool PAIR>
 __global__ __launch_bounds__(kScatWaves * 64) void k_scatter(const TextDesc *__restrict__ descs,
                                                              const uint32_t *__restrict__ bases,
                                                              uint32_t nd, uint32_t nitems, uint32_t g)
 {
-    __shared__ WaveSmem<E, REORDER> sm[kScatWaves];
+    __shared__ WaveSmem<E, REORDER, PAIR> sm[kScatWaves];
     const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (uint32_t item = blockIdx.x * kScatWaves + w; item < nitems;
          item += gridDim.x * kScatWaves) {
@@ -538,7 +576,7 @@ __global__ __launch_bounds__(kScatWaves * 64) void k_scatter(const TextDesc *__r
         if (d.b != sizeof(E) || g >= d.G || r >= d.nranges || (g + 1 < d.G) != REORDER) continue;
         const uint32_t Kg = group_bits(d, g);
         if (Kg == 0) continue;
-        wave_range<E, REORDER>(d, g, Kg, r, sm[w]);
+        wave_range<E, REORDER, PAIR>(d, g, Kg, r, sm[w]);
     }
 }
 
@@ -547,11 +585,14 @@ static void launch_width(const TextDesc *d_descs, const GroupLaunch &gl, uint32_
                          const LaunchCtx &ctx)
 {
     const dim3 block(kScatWaves * 64);
-    if (gl.rmask & 1u)
-        hipLaunchKernelGGL((k_scatter<E, false>), dim3(grid), block, 0, ctx.stream, d_descs,
+    if (gl.pair)  // one text, one group: WT and WM from the same splits
+        hipLaunchKernelGGL((k_scatter<E, false, true>), dim3(grid), block, 0, ctx.stream, d_descs,
                            gl.range_bases, gl.nd, gl.nranges, gl.g);
-    if (gl.rmask & 2u)
-        hipLaunchKernelGGL((k_scatter<E, true>), dim3(grid), block, 0, ctx.stream, d_descs,
+    else if (gl.rmask & 1u)
+        hipLaunchKernelGGL((k_scatter<E, false, false>), dim3(grid), block, 0, ctx.stream, d_descs,
+                           gl.range_bases, gl.nd, gl.nranges, gl.g);
+    if (!gl.pair && (gl.rmask & 2u))
+        hipLaunchKernelGGL((k_scatter<E, true, false>), dim3(grid), block, 0, ctx.stream, d_descs,
                            gl.range_bases, gl.nd, gl.nranges, gl.g);
 }
 

@@ -1,0 +1,73 @@
+"""Both structures of one text from one pass (wt_pair_build) on the GPU,
+against the oracle: the WT and the WM each equal the oracle's structure
+(levels, Z, directories), and equal the structures built one at a time."""
+import numpy as np
+import pytest
+
+from tests import pins
+from tests.gpu_util import assert_matches_oracle, gpu_build, lib
+
+pytestmark = pytest.mark.gpu
+
+WT, WM = 0, 1
+
+
+def _rand(n, L, seed, dtype=None):
+    rng = np.random.default_rng(seed)
+    if dtype is None:
+        dtype = np.uint8 if L <= 8 else (np.uint16 if L <= 16 else np.uint32)
+    return rng.integers(0, 1 << L, size=n, dtype=np.uint64).astype(dtype)
+
+
+def _pair(T, L):
+    import torch
+    B = lib()
+    wt, wm = B.pair_build(B.to_device(T), T.size, T.dtype.itemsize, L)
+    torch.cuda.synchronize()
+    return wt, wm
+
+
+def test_running_example(orc):
+    g = pins.read_golden()
+    T = np.array([int(x) for x in g["text"].split()], dtype=np.uint8)
+    wt, wm = _pair(T, 3)
+    for s, tag, kind in ((wt, "wt", WT), (wm, "wm", WM)):
+        bits, *_ = s.host_arrays()
+        assert [hex(int(w[0])) for w in bits] == g[f"{tag}_hex"].split()
+        assert_matches_oracle(orc, T, 3, kind, s)
+
+
+@pytest.mark.parametrize("L", [1, 2, 3, 7, 8])
+@pytest.mark.parametrize("n", [0, 1, 63, 64, 65, 2047, 2049, 4097, 70001])
+def test_edges(orc, n, L):
+    T = _rand(n, L, seed=3000 + n + L)
+    wt, wm = _pair(T, L)
+    assert_matches_oracle(orc, T, L, WT, wt)
+    assert_matches_oracle(orc, T, L, WM, wm)
+
+
+@pytest.mark.parametrize("dtype,L", [(np.uint16, 8), (np.uint32, 6), (np.uint16, 11), (np.uint32, 20)])
+def test_wide_symbols_and_more_groups(orc, dtype, L):
+    T = _rand(30011, L, seed=17, dtype=dtype)
+    wt, wm = _pair(T, L)
+    assert_matches_oracle(orc, T, L, WT, wt)
+    assert_matches_oracle(orc, T, L, WM, wm)
+
+
+def test_workload_shapes_equal_separate_builds(orc):
+    from paper_1702_07578_amd import inputs
+    for name, n in (("markov96", 600000), ("markov4", 500000), ("uniform256", 1 << 20)):
+        T, L = inputs.make(name, n)
+        wt, wm = _pair(T, L)
+        for s, kind in ((wt, WT), (wm, WM)):
+            d = gpu_build(T, L, kind)
+            got, want = s.host_arrays(), d.host_arrays()
+            assert all(np.array_equal(a, b) for a, b in zip(got[:2], want[:2])), (name, kind)
+            assert_matches_oracle(orc, T, L, kind, s)
+
+
+def test_range_error_reaches_both():
+    B = lib()
+    T = np.array([1, 2, 9, 3, 0], np.uint8)
+    wt, wm = _pair(T, 3)
+    assert wt.status() == B.WT_ERANGE and wm.status() == B.WT_ERANGE
