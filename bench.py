@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 COUNTERS = os.path.join(ROOT, "profiles", "scatter_markov96_counters.json")
+PAIR_COUNTERS = os.path.join(ROOT, "profiles", "pair_scatter_markov96_counters.json")
 SCATTER_SRC = os.path.join(ROOT, "paper_1702_07578_amd", "csrc", "wt_scatter.hip")
 
 
@@ -47,12 +48,12 @@ WORKLOAD_TEXT = {
 }
 
 
-def scatter_traffic(per_launch_alg_bytes):
+def scatter_traffic(per_launch_alg_bytes, path=COUNTERS):
     """HBM bytes per scatter launch from the committed counter runs, or None
     when there are none or the kernel source changed since they were taken."""
-    if not os.path.exists(COUNTERS):
+    if not os.path.exists(path):
         return None
-    c = json.load(open(COUNTERS))
+    c = json.load(open(path))
     src = hashlib.sha256(open(SCATTER_SRC, "rb").read()).hexdigest()
     if c.get("source_sha256") != src:
         return None
@@ -420,6 +421,48 @@ def main():
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": scatter_traffic(per_launch_bytes) if default_markov else None,
                 "alg_bytes_per_launch": int(per_launch_bytes), "avg_launch_ms": round(scat["avg_ms"], 4)}
+    # both structures from one pass (wt_pair_build): the same K steps, timed
+    # the same way, when the levels fit one group
+    pair = None
+    if L and L <= 8 and B.wt_pair_workspace_bytes(n, b, L):
+        pws = torch.empty(int(B.wt_pair_workspace_bytes(n, b, L)), dtype=torch.uint8, device=dev)
+        wt_s, wm_s = structs[B.WT_TREE], structs[B.WT_MATRIX]
+        for _ in range(args.warmup):
+            B.pair_build(d_text, n, b, L, ws=pws, out=(wt_s, wm_s))
+        torch.cuda.synchronize()
+        probe2 = B.EventRecorder(512)
+        probe2.pair_build(d_text, n, b, L, wt_s, wm_s, pws)
+        torch.cuda.synchronize()
+        rec2 = B.EventRecorder(probe2.used * args.steps + 8)
+        torch.cuda.synchronize()
+        pe0 = torch.cuda.Event(enable_timing=True)
+        pe1 = torch.cuda.Event(enable_timing=True)
+        pe0.record(stream)
+        for _ in range(args.steps):
+            rec2.pair_build(d_text, n, b, L, wt_s, wm_s, pws)
+        pe1.record(stream)
+        torch.cuda.synchronize()
+        pair_ms = pe0.elapsed_time(pe1) / args.steps
+        pkt = rec2.kernel_times(pe0)
+        pk = {name: {"launches": len(v), "avg_ms": sum(v) / len(v)} for name, v in pkt.items()}
+        pbytes = n * b + 2 * L * W * 8
+        pach = pbytes / (pk["scatter"]["avg_ms"] / 1e3) / 1e9
+        pair = {"ms_per_step": pair_ms, "value": 2 * n / (pair_ms / 1e3), "kernels": pk,
+                "roofline": {"kernel": "scatter (pair: WT and WM runs from one set of splits)", "bound": "hbm",
+                             "limiter": ("vector-instruction issue: about 91 VALU instructions per 64 symbols for "
+                                         "7 levels of both structures (rocprofv3 SQ_INSTS_VALU), about 66% of the "
+                                         "chip's issue rate at 3 waves per SIMD" if default_markov else
+                                         "vector-instruction issue (counters taken on markov96 only)"),
+                             "achieved": round(pach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": round(pach / HBM_PEAK_GBS, 4),
+                             "traffic": scatter_traffic(pbytes, PAIR_COUNTERS) if default_markov else None,
+                             "alg_bytes_per_launch": int(pbytes),
+                             "avg_launch_ms": round(pk["scatter"]["avg_ms"], 4)}}
+        for k, s in structs.items():
+            if s.status() != 0:
+                raise SystemExit(f"pair build status {s.status()} for kind {k}")
+        del pws
+
     # whole-build roofline: B_alg = 2 n b + L W 8 + directories, per build
     nb = W // 8
     dir_bytes = L * (nb + 1) * 4 + 2 * L * ((n + 4095) // 4096 + 1) * 4
@@ -534,6 +577,20 @@ def main():
 
     log(f"step {ms_per_step:.3f} ms; kernels per step: " +
         ", ".join(f"{k} {v['total_ms_per_step']:.3f}ms" for k, v in sorted(kernels.items(), key=lambda x: -x[1]['total_ms_per_step'])))
+    # the headline step: the WT and the WM of the text by the pair build when
+    # the levels fit one group (both structures from one pass), else by two
+    # builds; the other way is reported beside it
+    separate = {"ms_per_step": round(ms_per_step, 4), "value": round(value, 1), "roofline": roofline,
+                "build_alg_gbs": round(build_gbs, 1),
+                "kernels": {k: {"avg_ms": round(v["avg_ms"], 4), "launches_per_step": v["launches"] // args.steps}
+                            for k, v in kernels.items()}}
+    how = "WT build + WM build (wt_build, wm_build)"
+    if pair is not None:
+        ms_per_step, value, roofline = pair["ms_per_step"], pair["value"], pair["roofline"]
+        kernels = {k: {"avg_ms": v["avg_ms"], "launches": v["launches"]} for k, v in pair["kernels"].items()}
+        dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
+        build_gbs = 2 * b_alg_build / (ms_per_step / 1e3) / 1e9
+        how = "the WT and the WM by one pass (wt_pair_build)"
     out = {
         "metric": "WT+WM build throughput (symbols/s), one GPU",
         "value": round(value, 1),
@@ -548,8 +605,8 @@ def main():
         "dtype": f"u{8 * b}",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOAD_TEXT.get(args.workload, 'text')}, n={n} "
-                               f"uint{8 * b} symbols, {L} levels; step = WT build + WM build (levels, Z, "
-                               f"rank/select directories)",
+                               f"uint{8 * b} symbols, {L} levels; step = {how}, each with levels, Z and "
+                               f"rank/select directories",
                    "n": n, "sym_bytes": b, "lg_sigma": L, "tile_log2": args.tile_log2 or "auto",
                    "group_bits": args.group_bits or "auto"},
         "roofline": roofline,
@@ -562,6 +619,7 @@ def main():
         "queries_per_s": round(q_per_s, 1),
         "conversion": conv,
         "sort_strategy": ps_ms,
+        "separate_builds": separate if pair is not None else None,
     }
     print(json.dumps(out), flush=True)
 

@@ -323,6 +323,10 @@ int wt_build_recorded(wt_kind kind, const void *d_text, uint64_t n, uint32_t sym
                       uint32_t lg_sigma, wt_levels *out, void *d_ws, size_t ws_bytes,
                       const wt_tune *tune, hipStream_t stream, hipEvent_t *events,
                       uint32_t *kernel_ids, uint32_t capacity, uint32_t *recorded);
+/* wt_pair_build with the same event recording as wt_build_recorded */
+int wt_pair_build_recorded(const void *d_text, uint64_t n, uint32_t sym_bytes, uint32_t lg_sigma,
+                           wt_levels *wt, wt_levels *wm, void *d_ws, size_t ws_bytes, hipStream_t stream,
+                           hipEvent_t *events, uint32_t *kernel_ids, uint32_t capacity, uint32_t *recorded);
 
 /*
  * Profiling aid: run one build like wt_build_tuned, recording a HIP event

@@ -98,6 +98,8 @@ _SIGS = {
     "wt_merge": (_i, [_LP, _u32, _LP, _v, _sz, _v]),
     "wt_pair_workspace_bytes": (_sz, [_u64, _u32, _u32]),
     "wt_pair_build": (_i, [_v, _u64, _u32, _u32, _LP, _LP, _v, _sz, _v]),
+    "wt_pair_build_recorded": (_i, [_v, _u64, _u32, _u32, _LP, _LP, _v, _sz, _v, ctypes.POINTER(_v),
+                                    ctypes.POINTER(_u32), _u32, ctypes.POINTER(_u32)]),
     "wt_ps_workspace_bytes": (_sz, [_u64, _u32, _u32]),
     "wt_ps_build": (_i, [_i, _v, _u64, _u32, _u32, _LP, _v, _sz, _v]),
     "wt_export_pool_words": (_u64, [_u64, _u32]),
@@ -488,6 +490,25 @@ class EventRecorder:
                                 ctypes.c_void_p(ws.data_ptr()), ws.numel(), _tune_ptr(tune),
                                 _stream_handle(stream), hp, ip, cap, ctypes.byref(rec)),
               "wt_build_recorded")
+        if rec.value > cap:
+            raise WtError(WT_ENOSPACE, "EventRecorder capacity exceeded")
+        first = self.used
+        self.used += rec.value
+        return first, self.used
+
+    def pair_build(self, d_text, n, sym_bytes, L, wt, wm, ws, stream=None):
+        """Enqueue one pair build (WT and WM), recording an event after each kernel."""
+        rec = ctypes.c_uint32(0)
+        cap = self.capacity - self.used
+        if cap <= 0:
+            raise WtError(WT_ENOSPACE, "EventRecorder full")
+        hp = ctypes.cast(ctypes.byref(self.handles, self.used * ctypes.sizeof(ctypes.c_void_p)),
+                         ctypes.POINTER(ctypes.c_void_p))
+        ip = ctypes.cast(ctypes.byref(self.ids, self.used * 4), ctypes.POINTER(ctypes.c_uint32))
+        ptr = ctypes.c_void_p(d_text.data_ptr()) if n > 0 else ctypes.c_void_p(ws.data_ptr())
+        check(wt_pair_build_recorded(ptr, n, sym_bytes, L, ctypes.byref(wt.view), ctypes.byref(wm.view),
+                                     ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(stream), hp, ip,
+                                     cap, ctypes.byref(rec)), "wt_pair_build_recorded")
         if rec.value > cap:
             raise WtError(WT_ENOSPACE, "EventRecorder capacity exceeded")
         first = self.used

@@ -1131,6 +1131,20 @@ void rec_after(void *user, uint32_t kid)
 }
 }  // namespace
 
+extern "C" int wt_pair_build_recorded(const void *d_text, uint64_t n, uint32_t sym_bytes, uint32_t lg_sigma,
+                                      wt_levels *wt, wt_levels *wm, void *d_ws, size_t ws_bytes,
+                                      hipStream_t stream, hipEvent_t *events, uint32_t *kernel_ids,
+                                      uint32_t capacity, uint32_t *recorded)
+{
+    if ((capacity && (!events || !kernel_ids)) || !recorded) return WT_EINVAL;
+    RecState r{stream, events, kernel_ids, capacity, 0, false};
+    LaunchCtx ctx{stream, rec_after, &r};
+    int rc = pair_one(d_text, n, sym_bytes, lg_sigma, wt, wm, d_ws, ws_bytes, ctx);
+    *recorded = r.count;
+    if (rc == WT_OK && r.failed) rc = WT_EHIP;
+    return rc;
+}
+
 extern "C" int wt_build_recorded(wt_kind kind, const void *d_text, uint64_t n, uint32_t sym_bytes,
                                  uint32_t lg_sigma, wt_levels *out, void *d_ws, size_t ws_bytes,
                                  const wt_tune *tune, hipStream_t stream, hipEvent_t *events,
