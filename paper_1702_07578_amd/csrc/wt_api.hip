@@ -255,12 +255,14 @@ struct DevBases {
 };
 
 static hipError_t run_build(const TextDesc *d_descs, const Sched &s, const DevBases &b,
-                            uint32_t grid_cap, const LaunchCtx &ctx, bool pair = false)
+                            uint32_t grid_cap, const LaunchCtx &ctx, bool pair = false,
+                            uint32_t pair_bits = 0)
 {
     hipError_t e;
     for (uint32_t g = 0; g < s.gmax; g++) {
         GroupLaunch gl;
         gl.pair = pair;
+        gl.pair_bits = pair_bits;
         gl.g = g;
         gl.nd = s.nd;
         gl.range_bases = b.ranges;
@@ -356,7 +358,7 @@ static int pair_one(const void *d_text, uint64_t n, uint32_t b, uint32_t L, wt_l
     if (launch_init(p.d, d_desc, ctx) != hipSuccess) return WT_EHIP;
     DevBases bb;
     bb.walk.assign(s.walk_items.size(), nullptr);
-    if (run_build(d_desc, s, bb, 0, ctx, true) != hipSuccess) return WT_EHIP;
+    if (run_build(d_desc, s, bb, 0, ctx, true, p.d.K) != hipSuccess) return WT_EHIP;
     if (launch_dirs(d_desc2, nullptr, 1, s.dir_items, s.max_levels, false, 0, ctx) != hipSuccess)
         return WT_EHIP;
     return WT_OK;

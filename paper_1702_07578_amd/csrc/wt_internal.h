@@ -153,6 +153,7 @@ struct GroupLaunch {
     uint32_t rmask;    // bit 0: some text ends with group g; bit 1: some text goes on
     uint32_t grid_cap; // 0: one workgroup per item
     bool pair = false; // the pair scatter (WT and WM of one text, one group)
+    uint32_t pair_bits = 0;  // the pair's group width (its scatter is sized for it)
 };
 
 hipError_t launch_init(const TextDesc &d, TextDesc *d_dst, const LaunchCtx &ctx);

@@ -25,10 +25,6 @@
 namespace wtg {
 
 constexpr uint32_t kChunks = kWaveTile / 64;              // chunks of 64 symbols per tile
-constexpr uint32_t kRuns = (1u << kMaxGroupBits) - 1;      // (level, key) pairs of levels 0..K-1
-constexpr uint32_t kKeys = 1u << kMaxGroupBits;            // keys of level K (the finest)
-// full output words of one tile over all levels (<= kChunks per level)
-constexpr uint32_t kMaxWords = kMaxGroupBits * kChunks;
 // state of the word a key's run ends in (that word is G >> 6 of the key's
 // next run): none, kept in LDS, or kept with low bits that belong to
 // another range (that word is then completed by atomic OR)
@@ -37,36 +33,39 @@ constexpr uint8_t kNoPend = 0, kPend = 1, kPendForeign = 2;
 // One wave's LDS.  Tables of levels 0..Kg-1 are indexed lvl_off(a) + key.
 // REORDER (the group's symbols move on to the next group's sequence) adds
 // the tables of level Kg, the finest key.
-template <typename E, bool REORDER, bool PAIR>
+template <typename E, bool REORDER, bool PAIR, uint32_t KB>
 struct WaveSmem {
+    static constexpr uint32_t kRunsB = (1u << KB) - 1;  // (level, key) pairs of levels 0..KB-1
+    static constexpr uint32_t kKeysB = 1u << KB;        // keys of level KB (the finest)
+    static constexpr uint32_t kWordsB = KB * kChunks;   // full output words of one tile
     // level a of the tile in order a; while the tables are built (and at a
     // range start) it holds the finest key counts and their prefix sums
-    uint64_t bits[kMaxGroupBits][kChunks];
-    uint64_t pend_v[kRuns];  // bits so far of the word a key's run ends in
-    uint64_t pend_v2[PAIR ? kRuns : 1];  // the same for the pair's WM
-    uint32_t G[kRuns];       // global start of the key's bits for this tile
-    uint32_t G2[PAIR ? kRuns : 1];       // the same in the pair's WM
-    uint16_t h[kRuns];       // the tile's count of every key
-    uint16_t lo[kRuns];      // start of the key in the tile order of its level
-    uint8_t pend[kRuns];     // state of that word
-    uint8_t pend2[PAIR ? kRuns : 1];
-    uint32_t lvw[kMaxGroupBits];  // word offset of level a from the group's base pointer
-    uint32_t GK[REORDER ? kKeys : 1];
-    uint16_t hK[REORDER ? kKeys : 1];
-    uint16_t loK[REORDER ? kKeys : 1];
+    uint64_t bits[KB][kChunks];
+    uint64_t pend_v[kRunsB];  // bits so far of the word a key's run ends in
+    uint64_t pend_v2[PAIR ? kRunsB : 1];  // the same for the pair's WM
+    uint32_t G[kRunsB];       // global start of the key's bits for this tile
+    uint32_t G2[PAIR ? kRunsB : 1];       // the same in the pair's WM
+    uint16_t h[kRunsB];       // the tile's count of every key
+    uint16_t lo[kRunsB];      // start of the key in the tile order of its level
+    uint8_t pend[kRunsB];     // state of that word
+    uint8_t pend2[PAIR ? kRunsB : 1];
+    uint32_t lvw[KB];  // word offset of level a from the group's base pointer
+    uint32_t GK[REORDER ? kKeysB : 1];
+    uint16_t hK[REORDER ? kKeysB : 1];
+    uint16_t loK[REORDER ? kKeysB : 1];
     union alignas(16) {
         E elem[kWaveTile];  // the tile, in its next order (loading and splits)
         struct {            // copy-out, after the splits
-            uint16_t kw[kMaxWords];  // run of every full word
-            uint16_t wb[kRuns];      // first full word of every run, all levels
+            uint16_t kw[kWordsB];  // run of every full word
+            uint16_t wb[kRunsB];   // first full word of every run, all levels
         } co;
     };
 
-    __device__ uint32_t *tmp32() { return (uint32_t *)&bits[0][0]; }              // kKeys entries
-    __device__ uint16_t *tmp16() { return (uint16_t *)(tmp32() + kKeys); }        // kKeys + 1 entries
+    __device__ uint32_t *tmp32() { return (uint32_t *)&bits[0][0]; }              // kKeysB entries
+    __device__ uint16_t *tmp16() { return (uint16_t *)(tmp32() + kKeysB); }       // kKeysB + 1 entries
+    static_assert(sizeof(uint64_t) * KB * kChunks >= 4 * kKeysB + 2 * (kKeysB + 1),
+                  "level buffer too small for the table scratch");
 };
-static_assert(sizeof(uint64_t) * kMaxGroupBits * kChunks >= 4 * kKeys + 2 * (kKeys + 1),
-              "level buffer too small for the table scratch");
 
 // orders the wave's LDS accesses (the wave runs in lockstep; no s_barrier)
 __device__ inline void wave_sync()
@@ -151,9 +150,9 @@ __device__ inline uint32_t group_level0(const TextDesc &d, uint32_t g)
 
 // G at the first tile of range r: the range prefix of every finest key merged
 // upward, plus the key bases of each level.
-template <typename E, bool REORDER, bool PAIR>
+template <typename E, bool REORDER, bool PAIR, uint32_t KB>
 __device__ inline void wave_range_start(const TextDesc &d, uint32_t g, uint32_t Kg, uint32_t r,
-                                        WaveSmem<E, REORDER, PAIR> &sm)
+                                        WaveSmem<E, REORDER, PAIR, KB> &sm)
 {
     const uint32_t lane = lane_id();
     const uint32_t nk = 1u << Kg;
@@ -202,9 +201,9 @@ struct Side {
     uint64_t *base;
 };
 
-template <typename E, bool REORDER, bool PAIR>
+template <typename E, bool REORDER, bool PAIR, uint32_t KB>
 __device__ __attribute__((always_inline)) inline void copy_full_words(const TextDesc &d, uint32_t Kg,
-                                                                      WaveSmem<E, REORDER, PAIR> &sm,
+                                                                      WaveSmem<E, REORDER, PAIR, KB> &sm,
                                                                       const Side &sd)
 {
     const uint32_t lane = lane_id();
@@ -219,7 +218,7 @@ __device__ __attribute__((always_inline)) inline void copy_full_words(const Text
     for (uint32_t e = lane; e < nr; e += 64)
         if (full_words(G[e], sm.h[e]) != 0) sm.co.kw[sm.co.wb[e]] = (uint16_t)e;
     wave_sync();
-    constexpr uint32_t PER = (kMaxWords + 63) / 64;
+    constexpr uint32_t PER = (KB * kChunks + 63) / 64;
     uint32_t m = 0;
 #pragma unroll
     for (uint32_t i = 0; i < PER; i++) {
@@ -252,9 +251,9 @@ __device__ __attribute__((always_inline)) inline void copy_full_words(const Text
 // First and last word of every run (one lane per run, all levels): merged
 // with the word kept from earlier tiles of the range, stored when complete,
 // kept otherwise.
-template <typename E, bool REORDER, bool PAIR>
+template <typename E, bool REORDER, bool PAIR, uint32_t KB>
 __device__ __attribute__((always_inline)) inline void run_end_words(const TextDesc &d, uint32_t Kg,
-                                                                    WaveSmem<E, REORDER, PAIR> &sm,
+                                                                    WaveSmem<E, REORDER, PAIR, KB> &sm,
                                                                     const Side &sd)
 {
     uint64_t *base = sd.base;
@@ -306,10 +305,10 @@ __device__ __attribute__((always_inline)) inline void run_end_words(const TextDe
 // symbols whose bits are all one: they sort after every real symbol at every
 // level, so the real symbols keep their places and the padding fills the
 // end of every level's stream.
-template <typename E, bool REORDER, bool PAIR, bool SPLIT>
+template <typename E, bool REORDER, bool PAIR, uint32_t KB, bool SPLIT>
 __device__ __attribute__((always_inline)) inline void split_pass(uint32_t (&v)[kChunks], uint32_t a,
                                                                  uint32_t bit, uint32_t base1,
-                                                                 WaveSmem<E, REORDER, PAIR> &sm)
+                                                                 WaveSmem<E, REORDER, PAIR, KB> &sm)
 {
     const uint32_t lane = lane_id();
     uint32_t neg_lane = 0u - lane;
@@ -369,10 +368,10 @@ struct TileUnits {
 template <typename E>
 constexpr bool kPrefetch = sizeof(E) == 1;
 
-template <typename E, bool REORDER, bool PAIR>
+template <typename E, bool REORDER, bool PAIR, uint32_t KB>
 __device__ __attribute__((always_inline)) inline void wave_tile(const TextDesc &d, uint32_t g,
                                                                 uint32_t Kg, uint32_t t,
-                                                                WaveSmem<E, REORDER, PAIR> &sm,
+                                                                WaveSmem<E, REORDER, PAIR, KB> &sm,
                                                                 TileUnits<E> &tu, bool vec,
                                                                 bool have, uint32_t t1)
 {
@@ -478,7 +477,7 @@ __device__ __attribute__((always_inline)) inline void wave_tile(const TextDesc &
     for (uint32_t c = 0; c < kChunks; c++) v[c] = sm.elem[c * 64 + lane];
     wave_sync();
     for (uint32_t a = 0; a + 1 < Kg; a++) {
-        split_pass<E, REORDER, PAIR, true>(v, a, 1u << (shift + Kg - 1 - a), sm.lo[lvl_off(a + 1) + 1], sm);
+        split_pass<E, REORDER, PAIR, KB, true>(v, a, 1u << (shift + Kg - 1 - a), sm.lo[lvl_off(a + 1) + 1], sm);
         wave_sync();
 #pragma unroll
         for (uint32_t c = 0; c < kChunks; c++) v[c] = sm.elem[c * 64 + lane];
@@ -488,7 +487,7 @@ __device__ __attribute__((always_inline)) inline void wave_tile(const TextDesc &
         // the last split orders the tile by its reversed Kg-bit key: each
         // key's symbols, in text order, go to the key's place in the next
         // group's sequence (padding sorts last and is dropped)
-        split_pass<E, REORDER, PAIR, true>(v, Kg - 1, 1u << shift, sm.loK[1], sm);
+        split_pass<E, REORDER, PAIR, KB, true>(v, Kg - 1, 1u << shift, sm.loK[1], sm);
         wave_sync();
         E *gout = (E *)seq_out(d, g);
         for (uint32_t p = lane; p < len; p += 64) {
@@ -498,7 +497,7 @@ __device__ __attribute__((always_inline)) inline void wave_tile(const TextDesc &
             if (gi < d.n) gout[gi] = x;
         }
     } else {
-        split_pass<E, REORDER, PAIR, false>(v, Kg - 1, 1u << shift, 0u, sm);
+        split_pass<E, REORDER, PAIR, KB, false>(v, Kg - 1, 1u << shift, 0u, sm);
     }
     wave_sync();
 
@@ -524,13 +523,13 @@ __device__ __attribute__((always_inline)) inline void wave_tile(const TextDesc &
     wave_sync();
 }
 
-template <typename E, bool REORDER, bool PAIR>
+template <typename E, bool REORDER, bool PAIR, uint32_t KB>
 __device__ void wave_range(const TextDesc &d, uint32_t g, uint32_t Kg, uint32_t r,
-                           WaveSmem<E, REORDER, PAIR> &sm)
+                           WaveSmem<E, REORDER, PAIR, KB> &sm)
 {
     const uint32_t lane = lane_id();
     wave_range_start(d, g, Kg, r, sm);
-    for (uint32_t e = lane; e < kRuns; e += 64) {
+    for (uint32_t e = lane; e < (1u << KB) - 1; e += 64) {
         sm.pend[e] = kNoPend;
         if (PAIR) sm.pend2[e] = kNoPend;
     }
@@ -561,12 +560,12 @@ __device__ void wave_range(const TextDesc &d, uint32_t g, uint32_t Kg, uint32_t 
 // Work item = (text, range); wave w of workgroup b takes items
 // b * kScatWaves + w, then strides by the whole grid.  The REORDER variant
 // takes the texts whose symbols move on to another group after group g.
-template <typename E, bool REORDER, bool PAIR>
+template <typename E, bool REORDER, bool PAIR, uint32_t KB>
 __global__ __launch_bounds__(kScatWaves * 64) void k_scatter(const TextDesc *__restrict__ descs,
                                                              const uint32_t *__restrict__ bases,
                                                              uint32_t nd, uint32_t nitems, uint32_t g)
 {
-    __shared__ WaveSmem<E, REORDER, PAIR> sm[kScatWaves];
+    __shared__ WaveSmem<E, REORDER, PAIR, KB> sm[kScatWaves];
     const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (uint32_t item = blockIdx.x * kScatWaves + w; item < nitems;
          item += gridDim.x * kScatWaves) {
@@ -575,8 +574,8 @@ __global__ __launch_bounds__(kScatWaves * 64) void k_scatter(const TextDesc *__r
         const uint32_t r = item - item_base(bases, nd, ti);
         if (d.b != sizeof(E) || g >= d.G || r >= d.nranges || (g + 1 < d.G) != REORDER) continue;
         const uint32_t Kg = group_bits(d, g);
-        if (Kg == 0) continue;
-        wave_range<E, REORDER, PAIR>(d, g, Kg, r, sm[w]);
+        if (Kg == 0 || Kg > KB) continue;  // the tables hold KB levels (the host picks KB >= Kg)
+        wave_range<E, REORDER, PAIR, KB>(d, g, Kg, r, sm[w]);
     }
 }
 
@@ -585,14 +584,18 @@ static void launch_width(const TextDesc *d_descs, const GroupLaunch &gl, uint32_
                          const LaunchCtx &ctx)
 {
     const dim3 block(kScatWaves * 64);
-    if (gl.pair)  // one text, one group: WT and WM from the same splits
-        hipLaunchKernelGGL((k_scatter<E, false, true>), dim3(grid), block, 0, ctx.stream, d_descs,
+    constexpr uint32_t K8 = kMaxGroupBits;
+    if (gl.pair && gl.pair_bits <= 7)  // one text, one group: WT and WM from the same splits
+        hipLaunchKernelGGL((k_scatter<E, false, true, 7>), dim3(grid), block, 0, ctx.stream, d_descs,
+                           gl.range_bases, gl.nd, gl.nranges, gl.g);
+    else if (gl.pair)
+        hipLaunchKernelGGL((k_scatter<E, false, true, K8>), dim3(grid), block, 0, ctx.stream, d_descs,
                            gl.range_bases, gl.nd, gl.nranges, gl.g);
     else if (gl.rmask & 1u)
-        hipLaunchKernelGGL((k_scatter<E, false, false>), dim3(grid), block, 0, ctx.stream, d_descs,
+        hipLaunchKernelGGL((k_scatter<E, false, false, K8>), dim3(grid), block, 0, ctx.stream, d_descs,
                            gl.range_bases, gl.nd, gl.nranges, gl.g);
     if (!gl.pair && (gl.rmask & 2u))
-        hipLaunchKernelGGL((k_scatter<E, true, false>), dim3(grid), block, 0, ctx.stream, d_descs,
+        hipLaunchKernelGGL((k_scatter<E, true, false, K8>), dim3(grid), block, 0, ctx.stream, d_descs,
                            gl.range_bases, gl.nd, gl.nranges, gl.g);
 }
 
