@@ -449,9 +449,9 @@ def main():
         pach = pbytes / (pk["scatter"]["avg_ms"] / 1e3) / 1e9
         pair = {"ms_per_step": pair_ms, "value": 2 * n / (pair_ms / 1e3), "kernels": pk,
                 "roofline": {"kernel": "scatter (pair: WT and WM runs from one set of splits)", "bound": "hbm",
-                             "limiter": ("vector-instruction issue: about 91 VALU instructions per 64 symbols for "
-                                         "7 levels of both structures (rocprofv3 SQ_INSTS_VALU), about 66% of the "
-                                         "chip's issue rate at 3 waves per SIMD" if default_markov else
+                             "limiter": ("vector-instruction issue: about 92 VALU instructions per 64 symbols for "
+                                         "7 levels of both structures (rocprofv3 SQ_INSTS_VALU), about 74% of the "
+                                         "chip's issue rate at 4 waves per SIMD" if default_markov else
                                          "vector-instruction issue (counters taken on markov96 only)"),
                              "achieved": round(pach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": round(pach / HBM_PEAK_GBS, 4),
