@@ -91,9 +91,9 @@ typedef struct wt_levels {
 
 /* Optional tuning knobs; zero fields mean "choose automatically". */
 typedef struct wt_tune {
-    uint32_t tile_log2;  /* log2 of symbols per tile, 10..16 */
+    uint32_t tile_log2;  /* accepted and ignored: a tile is always 2048 symbols (one wave's registers) */
     uint32_t group_bits; /* levels handled per pass over the text, 1..8 */
-    uint32_t grid;       /* ranges of consecutive tiles per text, one workgroup each (0: 512) */
+    uint32_t grid;       /* ranges of consecutive tiles per text, one wave each (0: 12288) */
     uint32_t persist;    /* workgroups per launch, looping over all work items (0: one per item) */
 } wt_tune;
 
