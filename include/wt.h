@@ -223,8 +223,8 @@ int wt_merge(const wt_levels *parts, uint32_t count, wt_levels *dst, void *d_ws,
  * order).  With lg_sigma <= 8 (one group of levels) the WT's build writes the
  * WM as well: the tiles are split once, and every run of a level is copied
  * to its WT interval and to its WM interval; the histogram and border passes
- * are shared.  With more levels the two structures are built one after the
- * other.  wt (kind WT_TREE) and wm (kind WT_MATRIX) are bound for (n,
+ * are shared.  With more levels the WM is built and the WT is gathered from
+ * its intervals as wt_convert does.  wt (kind WT_TREE) and wm (kind WT_MATRIX) are bound for (n,
  * lg_sigma); both receive exactly what wt_build and wm_build write (levels,
  * Z, directories, status).  Workspace: wt_pair_workspace_bytes(n, sym_bytes,
  * lg_sigma).  Asynchronous on `stream`; argument errors as for wt_build_tuned.

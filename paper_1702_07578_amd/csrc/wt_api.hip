@@ -321,7 +321,8 @@ static int build_one(wt_kind kind, const void *d_text, uint64_t n, uint32_t sym_
 // Both structures of one text.  With one group, the WT's build also writes
 // the WM from the same tile splits (the two differ only in where each run of
 // a level goes: prefix order or bit-reversed order, Section 5.1); with more
-// groups, the two are built one after the other.
+// groups, the WM is built and the WT gathered from its intervals (the
+// conversion), which costs less than a second multi-group build.
 static int pair_one(const void *d_text, uint64_t n, uint32_t b, uint32_t L, wt_levels *wt,
                     wt_levels *wm, void *d_ws, size_t ws_bytes, const LaunchCtx &ctx)
 {
@@ -333,9 +334,14 @@ static int pair_one(const void *d_text, uint64_t n, uint32_t b, uint32_t L, wt_l
     if (n > 0 && !d_text) return WT_EINVAL;
     if ((uintptr_t)d_text % b) return WT_EINVAL;
     if (!d_ws) return WT_EINVAL;
-    if (p.d.G != 1 || L == 0) {
+    if (L == 0) {
         if ((rc = build_one(WT_TREE, d_text, n, b, L, wt, d_ws, ws_bytes, nullptr, ctx)) != WT_OK) return rc;
         return build_one(WT_MATRIX, d_text, n, b, L, wm, d_ws, ws_bytes, nullptr, ctx);
+    }
+    if (p.d.G != 1) {
+        if ((rc = build_one(WT_MATRIX, d_text, n, b, L, wm, d_ws, ws_bytes, nullptr, ctx)) != WT_OK) return rc;
+        // the build's workspace is free again once the stream passes it
+        return wt_convert(wm, wt, d_ws, ws_bytes, ctx.stream);
     }
     const uint64_t dsz = align_up(sizeof(TextDesc), 256);
     if (ws_bytes < p.bytes + 2 * dsz + 256) return WT_ENOSPACE;
@@ -371,7 +377,15 @@ static size_t pair_ws_bytes(uint64_t n, uint32_t b, uint32_t L)
     if (p.d.G == 1 && L > 0) return p.bytes + 2 * align_up(sizeof(TextDesc), 256) + 256;
     WsPlan q;
     if (plan_text(n, b, L, WT_MATRIX, nullptr, q) != WT_OK) return 0;
-    return std::max(p.bytes, q.bytes) + align_up(sizeof(TextDesc), 256) + 256;
+    size_t need = q.bytes + align_up(sizeof(TextDesc), 256) + 256;
+    if (L > 0) {
+        const size_t conv = wt_convert_workspace_bytes(n, L);
+        if (conv == 0) return 0;
+        need = std::max(need, conv);
+    } else {
+        need = std::max<size_t>(need, p.bytes + align_up(sizeof(TextDesc), 256) + 256);
+    }
+    return need;
 }
 
 }  // namespace wtg

@@ -150,9 +150,12 @@ __global__ __launch_bounds__(256) void k_cgather(wt_levels src, wt_levels dst, c
     dst.bits[(uint64_t)l * W + w] = val;
 }
 
+// Z of the source, and its status (a source built from symbols out of range
+// makes the destination just as unspecified)
 __global__ void k_ccopy_zeros(wt_levels src, wt_levels dst)
 {
     for (uint32_t l = threadIdx.x; l < dst.lg_sigma; l += blockDim.x) dst.zeros[l] = src.zeros[l];
+    if (threadIdx.x == 0) *dst.status = *src.status;
 }
 
 // U: 1^{c_0} 0 1^{c_1} 0 ... 1^{c_{s-1}} 0 over positions [0, n + s), zero

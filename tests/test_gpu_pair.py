@@ -66,8 +66,11 @@ def test_workload_shapes_equal_separate_builds(orc):
             assert_matches_oracle(orc, T, L, kind, s)
 
 
-def test_range_error_reaches_both():
+@pytest.mark.parametrize("L,dtype", [(3, np.uint8), (10, np.uint16)])
+def test_range_error_reaches_both(L, dtype):
+    """One group (one pass) and more groups (WM build, then the WT gathered
+    from it): an out-of-range symbol is reported by both structures."""
     B = lib()
-    T = np.array([1, 2, 9, 3, 0], np.uint8)
-    wt, wm = _pair(T, 3)
+    T = np.array([1, 2, (1 << L) + 1, 3, 0], dtype)
+    wt, wm = _pair(T, L)
     assert wt.status() == B.WT_ERANGE and wm.status() == B.WT_ERANGE
