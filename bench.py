@@ -421,10 +421,11 @@ def main():
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": scatter_traffic(per_launch_bytes) if default_markov else None,
                 "alg_bytes_per_launch": int(per_launch_bytes), "avg_launch_ms": round(scat["avg_ms"], 4)}
-    # both structures from one pass (wt_pair_build): the same K steps, timed
-    # the same way, when the levels fit one group
+    # both structures by the pair build (wt_pair_build): one pass when the
+    # levels fit one group, else the WM and the WT gathered from it; the
+    # same K steps, timed the same way
     pair = None
-    if L and L <= 8 and B.wt_pair_workspace_bytes(n, b, L):
+    if L and B.wt_pair_workspace_bytes(n, b, L):
         pws = torch.empty(int(B.wt_pair_workspace_bytes(n, b, L)), dtype=torch.uint8, device=dev)
         wt_s, wm_s = structs[B.WT_TREE], structs[B.WT_MATRIX]
         for _ in range(args.warmup):
@@ -445,13 +446,16 @@ def main():
         pair_ms = pe0.elapsed_time(pe1) / args.steps
         pkt = rec2.kernel_times(pe0)
         pk = {name: {"launches": len(v), "avg_ms": sum(v) / len(v)} for name, v in pkt.items()}
-        pbytes = n * b + 2 * L * W * 8
+        # one group: the pair scatter writes both structures' levels; more
+        # groups: the WM's scatter launches, one group each
+        pbytes = n * b + 2 * L * W * 8 if L <= 8 else (n * b + L * W * 8) / G
         pach = pbytes / (pk["scatter"]["avg_ms"] / 1e3) / 1e9
         pair = {"ms_per_step": pair_ms, "value": 2 * n / (pair_ms / 1e3), "kernels": pk,
-                "roofline": {"kernel": "scatter (pair: WT and WM runs from one set of splits)", "bound": "hbm",
+                "roofline": {"kernel": ("scatter (pair: WT and WM runs from one set of splits)" if L <= 8 else
+                                        "scatter (the WM's groups; the WT is gathered from the WM)"), "bound": "hbm",
                              "limiter": ("vector-instruction issue: about 92 VALU instructions per 64 symbols for "
                                          "7 levels of both structures (rocprofv3 SQ_INSTS_VALU), about 74% of the "
-                                         "chip's issue rate at 4 waves per SIMD" if default_markov else
+                                         "chip's issue rate at 4 waves per SIMD" if default_markov and L <= 8 else
                                          "vector-instruction issue (counters taken on markov96 only)"),
                              "achieved": round(pach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": round(pach / HBM_PEAK_GBS, 4),
@@ -590,7 +594,8 @@ def main():
         kernels = {k: {"avg_ms": v["avg_ms"], "launches": v["launches"]} for k, v in pair["kernels"].items()}
         dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
         build_gbs = 2 * b_alg_build / (ms_per_step / 1e3) / 1e9
-        how = "the WT and the WM by one pass (wt_pair_build)"
+        how = ("the WT and the WM by one pass (wt_pair_build)" if L <= 8 else
+               "the WM, then the WT gathered from its intervals (wt_pair_build)")
     out = {
         "metric": "WT+WM build throughput (symbols/s), one GPU",
         "value": round(value, 1),

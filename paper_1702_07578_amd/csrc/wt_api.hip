@@ -318,6 +318,12 @@ static int build_one(wt_kind kind, const void *d_text, uint64_t n, uint32_t sym_
     return WT_OK;
 }
 
+}  // namespace wtg
+// the conversion with a launch context (defined with the C entry points)
+static int convert_one(const wt_levels *src, wt_levels *dst, void *d_ws, size_t ws_bytes,
+                       const wtg::LaunchCtx &ctx);
+namespace wtg {
+
 // Both structures of one text.  With one group, the WT's build also writes
 // the WM from the same tile splits (the two differ only in where each run of
 // a level goes: prefix order or bit-reversed order, Section 5.1); with more
@@ -341,7 +347,7 @@ static int pair_one(const void *d_text, uint64_t n, uint32_t b, uint32_t L, wt_l
     if (p.d.G != 1) {
         if ((rc = build_one(WT_MATRIX, d_text, n, b, L, wm, d_ws, ws_bytes, nullptr, ctx)) != WT_OK) return rc;
         // the build's workspace is free again once the stream passes it
-        return wt_convert(wm, wt, d_ws, ws_bytes, ctx.stream);
+        return ::convert_one(wm, wt, d_ws, ws_bytes, ctx);
     }
     const uint64_t dsz = align_up(sizeof(TextDesc), 256);
     if (ws_bytes < p.bytes + 2 * dsz + 256) return WT_ENOSPACE;
@@ -582,6 +588,15 @@ static TextDesc dir_desc(uint64_t n, uint32_t levels, uint64_t *bits, uint32_t *
 
 int wt_convert(const wt_levels *src, wt_levels *dst, void *d_ws, size_t ws_bytes, hipStream_t stream)
 {
+    LaunchCtx ctx{stream, nullptr, nullptr};
+    return convert_one(src, dst, d_ws, ws_bytes, ctx);
+}
+
+}  // extern "C"
+
+static int convert_one(const wt_levels *src, wt_levels *dst, void *d_ws, size_t ws_bytes,
+                       const wtg::LaunchCtx &ctx)
+{
     if (!view_ok(src) || !view_ok(dst) || !d_ws) return WT_EINVAL;
     if (src->n != dst->n || src->lg_sigma != dst->lg_sigma || src->kind == dst->kind) return WT_EINVAL;
     const uint64_t n = src->n;
@@ -592,7 +607,6 @@ int wt_convert(const wt_levels *src, wt_levels *dst, void *d_ws, size_t ws_bytes
     if (ws_bytes < need) return WT_ENOSPACE;
     ConvWs w;
     conv_plan(n, L, (uint8_t *)align_up((uintptr_t)d_ws, 256), &w);
-    LaunchCtx ctx{stream, nullptr, nullptr};
     // the descriptor (and the destination's status and Z cleared) first
     TextDesc d = dir_desc(n, L, dst->bits, dst->rank_dir, dst->sel0, dst->sel1, dst->zeros, dst->status, w);
     if (launch_init(d, w.desc, ctx) != hipSuccess) return WT_EHIP;
@@ -604,6 +618,8 @@ int wt_convert(const wt_levels *src, wt_levels *dst, void *d_ws, size_t ws_bytes
     if (launch_dirs(w.desc, nullptr, 1, L * d.dir_chunks, L, false, 0, ctx) != hipSuccess) return WT_EHIP;
     return WT_OK;
 }
+
+extern "C" {
 
 // merge of partial structures: the walk of every piece (levels 0..L), the
 // (prefix, piece) starts of every level, the pieces' views, a descriptor and
