@@ -216,7 +216,9 @@ __device__ inline void ps_segment(const E *__restrict__ src, E *__restrict__ out
     const uint32_t per = (nq + 255) / 256;
     uint16_t *mycnt = cnt + w * nq;
     // 1. ranks within the wave's quarter
-    uint32_t a[kPsPer], rk[kPsPer];
+    // symbols, and their ranks (packed above 16-bit symbols: one register each)
+    constexpr bool kPack = sizeof(E) <= 2;
+    uint32_t a[kPsPer], rk[kPack ? 1 : kPsPer];
     const uint32_t base0 = w * (kPsSeg / 4) + lane;
 #pragma unroll
     for (uint32_t j = 0; j < kPsPer; j++) {
@@ -237,12 +239,14 @@ __device__ inline void ps_segment(const E *__restrict__ src, E *__restrict__ out
         }
         const uint32_t rank = mbcnt64(peers);
         const uint32_t num = (uint32_t)__popcll(peers);
-        rk[j] = 0;
+        uint32_t r = 0;
         if (ok) {
             const uint32_t base = mycnt[q];
-            rk[j] = base + rank;
+            r = base + rank;
             if (rank + 1 == num) mycnt[q] = (uint16_t)(base + num);  // the last lane of the prefix
         }
+        if constexpr (kPack) a[j] |= r << 16;
+        else rk[j] = r;
     }
     __syncthreads();
     // 2. wave offsets per prefix, and the prefixes' starts in the segment
@@ -265,11 +269,16 @@ __device__ inline void ps_segment(const E *__restrict__ src, E *__restrict__ out
     }
     uint32_t total;
     uint32_t st = block256_exscan(run, wsum, total);
+    // each wave's start of q in the staged segment (start of q plus the
+    // wave's offset), and the cursor made relative to the staged position
 #pragma unroll
     for (uint32_t k = 0; k < 8; k++) {
         const uint32_t q = t * per + k;
         if (k < per && q < nq) {
             sstart[q] = st;
+            cursor[q] -= st;
+#pragma unroll
+            for (uint32_t ww = 0; ww < 4; ww++) cnt[ww * nq + q] = (uint16_t)(cnt[ww * nq + q] + st);
             st += tot[k];
         }
     }
@@ -278,23 +287,26 @@ __device__ inline void ps_segment(const E *__restrict__ src, E *__restrict__ out
 #pragma unroll
     for (uint32_t j = 0; j < kPsPer; j++) {
         if (FULL || base0 + j * 64 < len) {
-            const uint32_t q = (a[j] >> shift) & (nq - 1);
-            stage[sstart[q] + cnt[w * nq + q] + rk[j]] = (E)a[j];
+            const uint32_t x = kPack ? (a[j] & 0xffffu) : a[j];
+            const uint32_t r = kPack ? (a[j] >> 16) : rk[kPack ? 0 : j];
+            const uint32_t q = (x >> shift) & (nq - 1);
+            stage[cnt[w * nq + q] + r] = (E)x;
         }
     }
     __syncthreads();
-    // 4. write out in runs
+    // 4. write out in runs: staged position p of prefix q goes to
+    //    cursor[q] + p (the cursor holds the global start minus the staged one)
 #pragma unroll 4
     for (uint32_t p = t; p < (FULL ? kPsSeg : len); p += 256) {
         const uint32_t x = (uint32_t)stage[p];
         const uint32_t q = (x >> shift) & (nq - 1);
-        out[cursor[q] + (p - sstart[q])] = (E)x;
+        out[cursor[q] + p] = (E)x;
     }
     __syncthreads();
-    // 5. cursors past the segment, counts cleared
+    // 5. cursors past the segment (back to global positions), counts cleared
     for (uint32_t q = t; q < nq; q += 256) {
         const uint32_t end = (q + 1 < nq) ? sstart[q + 1] : len;
-        cursor[q] += end - sstart[q];
+        cursor[q] += end;
         cnt[q] = cnt[nq + q] = cnt[2 * nq + q] = cnt[3 * nq + q] = 0;
     }
     __syncthreads();
