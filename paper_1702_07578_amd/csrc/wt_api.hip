@@ -5,6 +5,8 @@
 
 #include <algorithm>
 #include <cstring>
+#include <map>
+#include <tuple>
 #include <vector>
 
 #include "wt_internal.h"
@@ -183,6 +185,7 @@ struct Sched {
     std::vector<bool> any_levels;  // per group
     std::vector<uint32_t> rmask;   // per group: bit 0 last group of a text, bit 1 not last
     uint32_t bmask = 0;            // symbol widths present
+    uint32_t pmask = 0;            // scatter instantiations (GroupLaunch::pmask)
     uint32_t dir_items = 0, tmpdir_items = 0, max_levels = 0, max_tmp_levels = 0;
     std::vector<uint32_t> walk_items;  // per step
     uint32_t gather_items = 0;
@@ -225,6 +228,8 @@ static int schedule(const std::vector<TextDesc> &ds, Sched &s)
             s.rmask[g] |= (g + 1 < d.G) ? 2u : 1u;
         }
         s.bmask |= (d.b == 1) ? 1u : (d.b == 2 ? 2u : 4u);
+        if (d.pair) s.pmask |= (d.K <= 7) ? 2u : 4u;
+        else if (d.nranges) s.pmask |= 1u;
         s.max_levels = std::max(s.max_levels, d.L);
         if (deep) s.max_tmp_levels = std::max(s.max_tmp_levels, d.L - d.K);
     }
@@ -255,14 +260,12 @@ struct DevBases {
 };
 
 static hipError_t run_build(const TextDesc *d_descs, const Sched &s, const DevBases &b,
-                            uint32_t grid_cap, const LaunchCtx &ctx, bool pair = false,
-                            uint32_t pair_bits = 0)
+                            uint32_t grid_cap, const LaunchCtx &ctx)
 {
     hipError_t e;
     for (uint32_t g = 0; g < s.gmax; g++) {
         GroupLaunch gl;
-        gl.pair = pair;
-        gl.pair_bits = pair_bits;
+        gl.pmask = s.pmask;
         gl.g = g;
         gl.nd = s.nd;
         gl.range_bases = b.ranges;
@@ -370,7 +373,7 @@ static int pair_one(const void *d_text, uint64_t n, uint32_t b, uint32_t L, wt_l
     if (launch_init(p.d, d_desc, ctx) != hipSuccess) return WT_EHIP;
     DevBases bb;
     bb.walk.assign(s.walk_items.size(), nullptr);
-    if (run_build(d_desc, s, bb, 0, ctx, true, p.d.K) != hipSuccess) return WT_EHIP;
+    if (run_build(d_desc, s, bb, 0, ctx) != hipSuccess) return WT_EHIP;
     if (launch_dirs(d_desc2, nullptr, 1, s.dir_items, s.max_levels, false, 0, ctx) != hipSuccess)
         return WT_EHIP;
     return WT_OK;
@@ -936,8 +939,34 @@ const char *wt_strerror(int code)
 
 struct BatchPlan {
     std::vector<WsPlan> plans;
+    std::vector<int64_t> partner;  // for a WT paired with the WM of the same text: the WM's index
     uint64_t o_desc, o_bases, n_bases, o_texts, total;
 };
+
+// WT and WM items of the same text (same pointer, length, width, levels) with
+// one group of levels are built as a pair: the WT's descriptor writes both,
+// the WM's keeps its outputs and directories but gets no build work items.
+static void pair_items(const wt_batch_item *items, uint32_t count, BatchPlan &bp)
+{
+    bp.partner.assign(count, -1);
+    using Key = std::tuple<uintptr_t, uint64_t, uint32_t, uint32_t>;
+    std::map<Key, std::vector<uint32_t>> wms;  // unpaired WM items per text, in item order
+    for (uint32_t j = count; j-- > 0;)
+        if (items[j].kind == WT_MATRIX)
+            wms[Key((uintptr_t)items[j].d_text, items[j].n, items[j].sym_bytes, items[j].lg_sigma)].push_back(j);
+    for (uint32_t i = 0; i < count; i++) {
+        const TextDesc &di = bp.plans[i].d;
+        if (items[i].kind != WT_TREE || di.G != 1 || di.L == 0 || di.n == 0) continue;
+        auto it = wms.find(Key((uintptr_t)items[i].d_text, items[i].n, items[i].sym_bytes, items[i].lg_sigma));
+        if (it == wms.end() || it->second.empty()) continue;
+        const uint32_t j = it->second.back();
+        it->second.pop_back();
+        bp.partner[i] = j;
+        bp.plans[i].d.pair = 1;
+        bp.plans[j].d.nranges = 0;
+        bp.plans[j].d.nchunks = 0;
+    }
+}
 
 static int plan_batch(const wt_batch_item *items, uint32_t count, const wt_tune *tune,
                       BatchPlan &bp, Sched *sched)
@@ -953,8 +982,9 @@ static int plan_batch(const wt_batch_item *items, uint32_t count, const wt_tune 
         if (rc != WT_OK) return rc;
         text_off[i] = off_texts;
         off_texts = align_up(off_texts + bp.plans[i].bytes, 256);
-        ds[i] = bp.plans[i].d;
     }
+    pair_items(items, count, bp);
+    for (uint32_t i = 0; i < count; i++) ds[i] = bp.plans[i].d;
     Sched s;
     int rc = schedule(ds, s);
     if (rc != WT_OK) return rc;
@@ -1005,6 +1035,12 @@ static int batch_image(const wt_batch_item *items, uint32_t count, void *d_ws, s
         bind_ws(p, base + bp.o_texts + p.bytes);
         p.d.text = it.d_text;
         bind_out(p.d, *it.out);
+        if (bp.partner[i] >= 0) {
+            const wt_levels &o2 = *items[bp.partner[i]].out;
+            p.d.bits2 = o2.bits;
+            p.d.zeros2 = o2.zeros;
+            p.d.status2 = o2.status;
+        }
         ds[i] = p.d;
     }
     bi.img.assign(bp.o_texts, 0);

@@ -152,8 +152,9 @@ struct GroupLaunch {
     uint32_t bmask;    // symbol widths present: bit 0 (1 byte), 1 (2 bytes), 2 (4 bytes)
     uint32_t rmask;    // bit 0: some text ends with group g; bit 1: some text goes on
     uint32_t grid_cap; // 0: one workgroup per item
-    bool pair = false; // the pair scatter (WT and WM of one text, one group)
-    uint32_t pair_bits = 0;  // the pair's group width (its scatter is sized for it)
+    // scatter instantiations to launch: bit 0 single structures, bit 1 pairs
+    // (WT and WM of one text, one group) of at most 7 levels, bit 2 pairs of 8
+    uint32_t pmask = 1;
 };
 
 hipError_t launch_init(const TextDesc &d, TextDesc *d_dst, const LaunchCtx &ctx);

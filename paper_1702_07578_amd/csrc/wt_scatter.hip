@@ -573,8 +573,10 @@ __global__ __launch_bounds__(kScatWaves * 64) void k_scatter(const TextDesc *__r
         const TextDesc &d = descs[ti];
         const uint32_t r = item - item_base(bases, nd, ti);
         if (d.b != sizeof(E) || g >= d.G || r >= d.nranges || (g + 1 < d.G) != REORDER) continue;
+        if ((d.pair != 0) != PAIR) continue;  // pairs go to the pair instantiations only
         const uint32_t Kg = group_bits(d, g);
         if (Kg == 0 || Kg > KB) continue;  // the tables hold KB levels (the host picks KB >= Kg)
+        if (PAIR && KB == kMaxGroupBits && Kg < KB) continue;  // the 7-bit pair kernel takes those
         wave_range<E, REORDER, PAIR, KB>(d, g, Kg, r, sm[w]);
     }
 }
@@ -585,16 +587,18 @@ static void launch_width(const TextDesc *d_descs, const GroupLaunch &gl, uint32_
 {
     const dim3 block(kScatWaves * 64);
     constexpr uint32_t K8 = kMaxGroupBits;
-    if (gl.pair && gl.pair_bits <= 7)  // one text, one group: WT and WM from the same splits
+    // pairs: WT and WM of one text (one group) from the same splits
+    if (gl.g == 0 && (gl.pmask & 2u))
         hipLaunchKernelGGL((k_scatter<E, false, true, 7>), dim3(grid), block, 0, ctx.stream, d_descs,
                            gl.range_bases, gl.nd, gl.nranges, gl.g);
-    else if (gl.pair)
+    if (gl.g == 0 && (gl.pmask & 4u))
         hipLaunchKernelGGL((k_scatter<E, false, true, K8>), dim3(grid), block, 0, ctx.stream, d_descs,
                            gl.range_bases, gl.nd, gl.nranges, gl.g);
-    else if (gl.rmask & 1u)
+    if (!(gl.pmask & 1u)) return;
+    if (gl.rmask & 1u)
         hipLaunchKernelGGL((k_scatter<E, false, false, K8>), dim3(grid), block, 0, ctx.stream, d_descs,
                            gl.range_bases, gl.nd, gl.nranges, gl.g);
-    if (!gl.pair && (gl.rmask & 2u))
+    if (gl.rmask & 2u)
         hipLaunchKernelGGL((k_scatter<E, true, false, K8>), dim3(grid), block, 0, ctx.stream, d_descs,
                            gl.range_bases, gl.nd, gl.nranges, gl.g);
 }

@@ -159,3 +159,62 @@ def test_batch_argument_errors():
     b.build()
     torch.cuda.synchronize()
     assert items[0][5].status() == 0
+
+
+def test_batch_pairs_share_one_pass(orc):
+    """WT and WM items of the same device text are built as pairs (one pass
+    writes both) inside a batch that also holds unpaired items: a WT without
+    its WM, a second WM of a paired text, a text of 8 levels (the 8-bit pair
+    kernel), one of 12 levels (never paired) and texts of their own.  Every
+    output equals the oracle and its standalone build, eagerly and on graph
+    replays."""
+    import torch
+    B = lib()
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(29)
+    shared = [
+        (rng.integers(0, 1 << 7, 70001).astype(np.uint8), 7, (WT, WM)),
+        (rng.integers(0, 1 << 8, 5000).astype(np.uint8), 8, (WM, WT)),
+        (rng.integers(0, 1 << 3, 3).astype(np.uint8), 3, (WT, WM, WM)),
+        (rng.integers(0, 1 << 5, 9000).astype(np.uint16), 5, (WT,)),
+        (rng.integers(0, 1 << 12, 6000).astype(np.uint16), 12, (WT, WM)),
+        (rng.integers(0, 1 << 2, 2049).astype(np.uint8), 2, (WM, WT)),
+    ]
+    texts, items = [], []
+    for T, L, kinds in shared:
+        d = B.to_device(T, dev)
+        for kind in kinds:
+            texts.append((T, L, kind))
+            items.append((d, T.size, T.dtype.itemsize, L, kind, B.Structure(T.size, L, kind, device=dev)))
+    for T, L, kind in _batch(10, seed=31, lo_exp=8.0, hi_exp=14.0):
+        texts.append((T, L, kind))
+        items.append((B.to_device(T, dev), T.size, T.dtype.itemsize, L, kind, B.Structure(T.size, L, kind, device=dev)))
+    _garble(items)
+    batch = B.Batch(items, tune=B.make_tune(persist=48))
+    batch.build()
+    torch.cuda.synchronize()
+    want = []
+    for (T, L, kind), it in zip(texts, items):
+        assert_matches_oracle(orc, T, L, kind, it[5])
+        alone = gpu_build(T, L, kind)
+        got = _defined(it[5], T.size)
+        for a, b in zip(got, _defined(alone, T.size)):
+            assert np.array_equal(a, b)
+        want.append(got)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        batch.prepare(side)
+        with torch.cuda.graph(g, stream=side):
+            batch.launch(side)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    for _ in range(2):
+        _garble(items)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for w, it in zip(want, items):
+            for a, b in zip(w, _defined(it[5], it[1])):
+                assert np.array_equal(a, b)
