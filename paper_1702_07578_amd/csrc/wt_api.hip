@@ -228,7 +228,8 @@ static int schedule(const std::vector<TextDesc> &ds, Sched &s)
             s.rmask[g] |= (g + 1 < d.G) ? 2u : 1u;
         }
         s.bmask |= (d.b == 1) ? 1u : (d.b == 2 ? 2u : 4u);
-        if (d.pair) s.pmask |= (d.K <= 7) ? 2u : 4u;
+        if (d.pair && d.G > 1) s.pmask |= 8u | 1u;  // group 0 paired, the rest single
+        else if (d.pair) s.pmask |= (d.K <= 7) ? 2u : 4u;
         else if (d.nranges) s.pmask |= 1u;
         s.max_levels = std::max(s.max_levels, d.L);
         if (deep) s.max_tmp_levels = std::max(s.max_tmp_levels, d.L - d.K);
@@ -943,9 +944,13 @@ struct BatchPlan {
     uint64_t o_desc, o_bases, n_bases, o_texts, total;
 };
 
-// WT and WM items of the same text (same pointer, length, width, levels) with
-// one group of levels are built as a pair: the WT's descriptor writes both,
-// the WM's keeps its outputs and directories but gets no build work items.
+// WT and WM items of the same text (same pointer, length, width, levels) are
+// built as a pair.  One group of levels: the WT's descriptor writes both, the
+// WM's keeps its outputs and directories but gets no build work items.  More
+// groups (of the full width): the WM's descriptor writes the WT's levels of
+// group 0 as well and seeds its walk; the WT's gets no scatter work and
+// gathers its deeper levels from the WM's (its temporary levels are the
+// WM's levels).
 static void pair_items(const wt_batch_item *items, uint32_t count, BatchPlan &bp)
 {
     bp.partner.assign(count, -1);
@@ -956,15 +961,23 @@ static void pair_items(const wt_batch_item *items, uint32_t count, BatchPlan &bp
             wms[Key((uintptr_t)items[j].d_text, items[j].n, items[j].sym_bytes, items[j].lg_sigma)].push_back(j);
     for (uint32_t i = 0; i < count; i++) {
         const TextDesc &di = bp.plans[i].d;
-        if (items[i].kind != WT_TREE || di.G != 1 || di.L == 0 || di.n == 0) continue;
+        if (items[i].kind != WT_TREE || di.L == 0 || di.n == 0) continue;
+        if (di.G > 1 && di.K != kMaxGroupBits) continue;
         auto it = wms.find(Key((uintptr_t)items[i].d_text, items[i].n, items[i].sym_bytes, items[i].lg_sigma));
         if (it == wms.end() || it->second.empty()) continue;
         const uint32_t j = it->second.back();
         it->second.pop_back();
-        bp.partner[i] = j;
-        bp.plans[i].d.pair = 1;
-        bp.plans[j].d.nranges = 0;
-        bp.plans[j].d.nchunks = 0;
+        if (di.G == 1) {
+            bp.partner[i] = j;  // the WT writes the WM too
+            bp.plans[i].d.pair = 1;
+            bp.plans[j].d.nranges = 0;
+            bp.plans[j].d.nchunks = 0;
+        } else {
+            bp.partner[j] = i;  // the WM writes the WT's first group
+            bp.plans[j].d.pair = 1;
+            bp.plans[i].d.nranges = 0;
+            bp.plans[i].d.nchunks = 0;
+        }
     }
 }
 
@@ -1035,13 +1048,22 @@ static int batch_image(const wt_batch_item *items, uint32_t count, void *d_ws, s
         bind_ws(p, base + bp.o_texts + p.bytes);
         p.d.text = it.d_text;
         bind_out(p.d, *it.out);
-        if (bp.partner[i] >= 0) {
-            const wt_levels &o2 = *items[bp.partner[i]].out;
-            p.d.bits2 = o2.bits;
-            p.d.zeros2 = o2.zeros;
-            p.d.status2 = o2.status;
-        }
         ds[i] = p.d;
+    }
+    // pairs: the primary writes the partner's outputs; a deep WT partner takes
+    // the WM's levels as its temporary levels
+    for (uint32_t i = 0; i < count; i++) {
+        if (bp.partner[i] < 0) continue;
+        TextDesc &d = ds[i];
+        TextDesc &o = ds[bp.partner[i]];
+        d.bits2 = o.bits;
+        d.zeros2 = o.zeros;
+        d.status2 = o.status;
+        if (d.kind == WT_MATRIX) {
+            d.walk2 = o.walk;
+            o.tmp_bits = d.bits + (uint64_t)d.K * d.W;
+            o.tmp_rank = d.rank_dir + (uint64_t)d.K * d.rank_stride;
+        }
     }
     bi.img.assign(bp.o_texts, 0);
     std::memcpy(bi.img.data() + bp.o_desc, ds.data(), count * sizeof(TextDesc));

@@ -288,8 +288,9 @@ __global__ __launch_bounds__(kBorderThreads) void k_borders(const TextDesc *__re
                 if (d.pair) d.zeros2[g * d.K + tid] = z;
             }
             // deep WT: intervals of the K-bit prefixes (level K) seed the walk
-            if (d.kind == WT_TREE && d.G > 1 && g == 0) {
-                uint32_t *tab = d.walk;  // walk_off(K, K) == 0
+            // (of this WT, or of the WT paired with this WM)
+            if (d.G > 1 && g == 0 && (d.kind == WT_TREE || d.pair)) {
+                uint32_t *tab = d.kind == WT_TREE ? d.walk : d.walk2;  // walk_off(K, K) == 0
                 for (uint32_t q = tid; q < nk; q += kBorderThreads) {
                     tab[q] = kbpi[lvl_off(Kg) + q];
                     tab[nk + q] = tot[lvl_off(Kg) + q];
@@ -335,8 +336,8 @@ __global__ __launch_bounds__(kBorderThreads) void k_borders(const TextDesc *__re
                 const uint32_t raw = sw[(kk + 1) << sh] - sw[kk << sh];
                 const uint32_t gs = raw + kb[e];
                 if ((gs & 63) != 0 && (gs >> 6) < d.W) level_ptr(d, g, a)[gs >> 6] = 0;
-                if (d.pair) {  // the WM of the pair: bit-reversed order
-                    const uint32_t gs2 = raw + kbpi[e];
+                if (d.pair && g == 0) {  // the pair's other structure, in its order
+                    const uint32_t gs2 = raw + (d.kind == WT_MATRIX ? kbid : kbpi)[e];
                     if ((gs2 & 63) != 0 && (gs2 >> 6) < d.W) d.bits2[(uint64_t)a * d.W + (gs2 >> 6)] = 0;
                 }
             }
@@ -346,7 +347,7 @@ __global__ __launch_bounds__(kBorderThreads) void k_borders(const TextDesc *__re
                 for (uint32_t a = 0; a < Kg; a++) {
                     uint64_t *out = level_ptr(d, g, a);
                     for (uint64_t wd = (d.n >> 6) + lane; wd < d.W; wd += 64) out[wd] = 0;
-                    if (d.pair)
+                    if (d.pair && g == 0)
                         for (uint64_t wd = (d.n >> 6) + lane; wd < d.W; wd += 64) d.bits2[(uint64_t)a * d.W + wd] = 0;
                 }
             }

@@ -68,12 +68,16 @@ struct TextDesc {
     uint32_t *walk;        // WT only, G > 1: per level l in [K,L): 3 x 2^l u32
     uint16_t *dir_bc;      // [Lall][nb] ones per 512-bit block
     uint32_t *dir_cs;      // [Lall][dir_chunks] chunk sums -> prefixes
-    // pair build (a WT desc with one group): the WM of the same text is
-    // written as well, from the same splits, into these outputs
+    // pair build: the other structure of the same text is written as well,
+    // from the same splits of group 0, into these outputs (a WT desc of one
+    // group writes its WM; a WM desc of several groups writes its WT's levels
+    // of group 0 and seeds that WT's interval walk, walk2; the WT gathers its
+    // deeper levels from the WM's)
     uint32_t pair;
     uint64_t *bits2;
     uint64_t *zeros2;
     int32_t *status2;
+    uint32_t *walk2;
 };
 
 // Construction by sorting (the second strategy): text cut into P chunks of C
@@ -153,7 +157,8 @@ struct GroupLaunch {
     uint32_t rmask;    // bit 0: some text ends with group g; bit 1: some text goes on
     uint32_t grid_cap; // 0: one workgroup per item
     // scatter instantiations to launch: bit 0 single structures, bit 1 pairs
-    // (WT and WM of one text, one group) of at most 7 levels, bit 2 pairs of 8
+    // (WT and WM of one text, one group) of at most 7 levels, bit 2 pairs of
+    // 8, bit 3 pairs whose text goes on to more groups (group 0 only)
     uint32_t pmask = 1;
 };
 

@@ -171,7 +171,8 @@ __device__ inline void wave_range_start(const TextDesc &d, uint32_t g, uint32_t 
         for (uint32_t k = lane; k < (1u << a); k += 64) {
             const uint32_t raw = sm.G[lvl_off(a) + k];
             sm.G[lvl_off(a) + k] = raw + kb[k];
-            if (PAIR) sm.G2[lvl_off(a) + k] = raw + d.KBpi[lvl_off(a) + k];  // the WM: bit-reversed order
+            // the other structure: bit-reversed order for a WM, prefix order for a WT
+            if (PAIR) sm.G2[lvl_off(a) + k] = raw + (d.kind == WT_MATRIX ? d.KBid : d.KBpi)[lvl_off(a) + k];
         }
     }
     if (REORDER) {
@@ -573,7 +574,7 @@ __global__ __launch_bounds__(kScatWaves * 64) void k_scatter(const TextDesc *__r
         const TextDesc &d = descs[ti];
         const uint32_t r = item - item_base(bases, nd, ti);
         if (d.b != sizeof(E) || g >= d.G || r >= d.nranges || (g + 1 < d.G) != REORDER) continue;
-        if ((d.pair != 0) != PAIR) continue;  // pairs go to the pair instantiations only
+        if ((d.pair != 0 && g == 0) != PAIR) continue;  // pairs' group 0 goes to the pair instantiations
         const uint32_t Kg = group_bits(d, g);
         if (Kg == 0 || Kg > KB) continue;  // the tables hold KB levels (the host picks KB >= Kg)
         if (PAIR && KB == kMaxGroupBits && Kg < KB) continue;  // the 7-bit pair kernel takes those
@@ -593,6 +594,9 @@ static void launch_width(const TextDesc *d_descs, const GroupLaunch &gl, uint32_
                            gl.range_bases, gl.nd, gl.nranges, gl.g);
     if (gl.g == 0 && (gl.pmask & 4u))
         hipLaunchKernelGGL((k_scatter<E, false, true, K8>), dim3(grid), block, 0, ctx.stream, d_descs,
+                           gl.range_bases, gl.nd, gl.nranges, gl.g);
+    if (gl.g == 0 && (gl.pmask & 8u))
+        hipLaunchKernelGGL((k_scatter<E, true, true, K8>), dim3(grid), block, 0, ctx.stream, d_descs,
                            gl.range_bases, gl.nd, gl.nranges, gl.g);
     if (!(gl.pmask & 1u)) return;
     if (gl.rmask & 1u)

@@ -162,12 +162,13 @@ def test_batch_argument_errors():
 
 
 def test_batch_pairs_share_one_pass(orc):
-    """WT and WM items of the same device text are built as pairs (one pass
-    writes both) inside a batch that also holds unpaired items: a WT without
-    its WM, a second WM of a paired text, a text of 8 levels (the 8-bit pair
-    kernel), one of 12 levels (never paired) and texts of their own.  Every
-    output equals the oracle and its standalone build, eagerly and on graph
-    replays."""
+    """WT and WM items of the same device text are built as pairs inside a
+    batch that also holds unpaired items: one group (one pass writes both; 7-
+    and 8-level pair kernels), more groups (the WM writes the WT's first group
+    and the WT gathers the rest from the WM: 12, 16 and 20 levels), a WT
+    without its WM, a second WM or WT of a paired text, and texts of their
+    own.  Every output equals the oracle and its standalone build, eagerly and
+    on graph replays."""
     import torch
     B = lib()
     dev = torch.device("cuda:0")
@@ -178,6 +179,8 @@ def test_batch_pairs_share_one_pass(orc):
         (rng.integers(0, 1 << 3, 3).astype(np.uint8), 3, (WT, WM, WM)),
         (rng.integers(0, 1 << 5, 9000).astype(np.uint16), 5, (WT,)),
         (rng.integers(0, 1 << 12, 6000).astype(np.uint16), 12, (WT, WM)),
+        (rng.integers(0, 1 << 20, 9001).astype(np.uint32), 20, (WM, WT)),
+        ((np.arange(30000) * 7919 % 65521).astype(np.uint16), 16, (WT, WM, WT)),
         (rng.integers(0, 1 << 2, 2049).astype(np.uint8), 2, (WM, WT)),
     ]
     texts, items = [], []
