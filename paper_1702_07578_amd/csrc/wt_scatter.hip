@@ -127,13 +127,16 @@ __device__ __attribute__((always_inline)) inline void static_for(F &&f)
 template <uint32_t c>
 __device__ inline void put_lane(uint32_t &acc_lo, uint32_t &acc_hi, uint64_t B)
 {
+    // B was just written by a vector compare; the compiler does not see into
+    // this block, so it does not insert the wait states a vector read of
+    // that SGPR pair needs: the s_nop gives them (the lane select is an
+    // inline constant)
     asm volatile(
-        "s_mov_b32 m0, %4\n\t"
-        "v_writelane_b32 %0, %2, m0\n\t"
-        "v_writelane_b32 %1, %3, m0"
+        "s_nop 1\n\t"
+        "v_writelane_b32 %0, %2, %4\n\t"
+        "v_writelane_b32 %1, %3, %4"
         : "+v"(acc_lo), "+v"(acc_hi)
-        : "s"((uint32_t)B), "s"((uint32_t)(B >> 32)), "n"(c)
-        : "m0");
+        : "s"((uint32_t)B), "s"((uint32_t)(B >> 32)), "n"(c));
 }
 
 // Base of the bit vectors group g writes: the output levels, or, for the
