@@ -4,7 +4,9 @@ the oracle supplies sampled level bits (its per-position definition), and
 every other output is checked through properties that hold at any size:
 the zero count of every level, the popcount of every level, the padding
 bits, the directories of every level recomputed by the oracle from the
-GPU's level words, and access at sampled positions."""
+GPU's level words, and access at sampled positions.  The pair build (both
+structures of the text, the benchmark's step) must write exactly the same
+outputs as the checked separate builds."""
 import numpy as np
 import pytest
 
@@ -69,10 +71,42 @@ def test_workload_full_size(orc, workload):
     print(f"[full-size] {workload}: n={T.size} b={T.dtype.itemsize} L={L}", flush=True)
     d = B.to_device(T)
     rng = np.random.default_rng(7)
+    built = {}
     for kind in (WT, WM):
         s = B.build(d, T.size, T.dtype.itemsize, L, kind)
         torch.cuda.synchronize()
         _check_structure(orc, T, L, kind, s, rng)
         _check_access(T, s, rng)
-        del s
-        torch.cuda.empty_cache()
+        built[kind] = s
+    # the pair build (the benchmark's step) writes exactly what the checked
+    # separate builds wrote: level words, Z and the defined directory entries
+    wt, wm = B.pair_build(d, T.size, T.dtype.itemsize, L)
+    torch.cuda.synchronize()
+    for kind, p in ((WT, wt), (WM, wm)):
+        assert p.status() == 0
+        assert _same_outputs(p, built[kind], T.size), f"pair build kind {kind} differs from the separate build"
+    del built, wt, wm
+    torch.cuda.empty_cache()
+
+
+def _same_outputs(a, b, n):
+    """Equal level words, Z, rank entries 0..W/8 and select samples up to
+    ceil(n/4096)+1 of every level, compared on the device."""
+    import torch
+    va, vb = a.view, b.view
+    L, W = a.L, va.words_per_level
+    cap = -(-n // 4096) + 1
+
+    def region(s, ptr, count, itemsize):
+        return s._slice(ptr, count, itemsize)
+
+    if not torch.equal(region(a, va.bits, L * W, 8), region(b, vb.bits, L * W, 8)):
+        return False
+    if not torch.equal(region(a, va.zeros, L, 8), region(b, vb.zeros, L, 8)):
+        return False
+    for l in range(L):
+        for pa, pb, stride, cnt in ((va.rank_dir, vb.rank_dir, va.rank_stride, W // 8 + 1),
+                                    (va.sel0, vb.sel0, va.sel_stride, cap), (va.sel1, vb.sel1, va.sel_stride, cap)):
+            if not torch.equal(region(a, pa + l * stride * 4, cnt, 4), region(b, pb + l * stride * 4, cnt, 4)):
+                return False
+    return True
