@@ -403,20 +403,60 @@ __global__ __launch_bounds__(256) void k_gather(const TextDesc *__restrict__ des
                                                 const uint32_t *__restrict__ bases, uint32_t nd,
                                                 uint32_t nitems)
 {
-    const uint32_t item = blockIdx.x * blockDim.x + threadIdx.x;
-    if (item >= nitems) return;
-    const uint32_t ti = find_text(bases, nd, item);
-    const TextDesc &d = descs[ti];
-    const uint64_t idx = item - item_base(bases, nd, ti);
-    if (d.kind != WT_TREE || d.G <= 1) return;
-    const uint64_t Wg = d.W / kGatherWords;  // W is a multiple of 8
-    const uint32_t l = d.K + (uint32_t)(idx / Wg);
-    if (l >= d.L) return;
-    const uint64_t w0 = (idx % Wg) * kGatherWords;
+    // the intervals of the first and the last word of the block (when they
+    // belong to the same text and level, every word of the block between
+    // them lies in an interval between theirs)
+    __shared__ uint32_t b_ti[2], b_l[2], b_p[2];
+    const uint32_t first = blockIdx.x * blockDim.x;
+    const uint32_t item = first + threadIdx.x;
+    const uint32_t last = min(nitems, first + blockDim.x) - 1;
+    bool ok = item < nitems;
+    uint32_t ti = 0, l = 0, np = 1;
+    uint64_t w0 = 0;
+    const TextDesc *dp = nullptr;
+    const uint32_t *tab = nullptr;
+    if (ok) {
+        ti = find_text(bases, nd, item);
+        dp = &descs[ti];
+        const uint64_t idx = item - item_base(bases, nd, ti);
+        ok = dp->kind == WT_TREE && dp->G > 1;
+        if (ok) {
+            const uint64_t Wg = dp->W / kGatherWords;  // W is a multiple of 8
+            l = dp->K + (uint32_t)(idx / Wg);
+            ok = l < dp->L;
+            w0 = (idx % Wg) * kGatherWords;
+            np = 1u << l;
+            tab = dp->walk + walk_off(dp->K, l);
+        }
+    }
+    // largest p in [a, b) with wt_start[p] <= pos (wt_start[a] <= pos)
+    auto search = [&](uint64_t pos, uint32_t a, uint32_t b) -> uint32_t {
+        while (b - a > 1) {
+            const uint32_t mid = (a + b) >> 1;
+            if (tab[2 * np + mid] <= pos) a = mid;
+            else b = mid;
+        }
+        return a;
+    };
+    // slot 0: the block's first item, slot 1: its last (the same thread when
+    // the block holds one item); positions past the text end clamp to n - 1
+    for (uint32_t slot = 0; slot < 2; slot++) {
+        if (item != (slot ? last : first)) continue;
+        b_ti[slot] = ok ? ti : 0xFFFFFFFFu;
+        b_l[slot] = l;
+        const uint64_t p0 = (w0 << 6) + (slot ? kGatherWords * 64 - 1 : 0);
+        b_p[slot] = ok ? search(min(p0, dp->n - 1), 0, np) : 0u;
+    }
+    __syncthreads();
+    if (!ok) return;
+    const TextDesc &d = *dp;
+    uint32_t ra = 0, rb = np;  // search range of the first piece of a word
+    if (b_ti[0] == ti && b_ti[1] == ti && b_l[0] == l && b_l[1] == l) {
+        ra = b_p[0];
+        rb = b_p[1] + 1;
+    }
     uint64_t *out = d.bits + (uint64_t)l * d.W;
     const uint64_t *wm = d.tmp_bits + (uint64_t)(l - d.K) * d.W;
-    const uint32_t np = 1u << l;
-    const uint32_t *tab = d.walk + walk_off(d.K, l);
     uint32_t lo = np;  // interval of the previous piece (none yet)
     for (uint32_t k = 0; k < kGatherWords; k++) {
         const uint64_t ws = (w0 + k) << 6;
@@ -425,19 +465,12 @@ __global__ __launch_bounds__(256) void k_gather(const TextDesc *__restrict__ des
         uint64_t pos = ws;
         while (pos < we) {
             // the non-empty interval holding pos: the previous one or the
-            // next one when they hold it, else the largest p with
-            // wt_start[p] <= pos (found by binary search)
+            // next one when they hold it, else a search
             if (lo < np && tab[2 * np + lo] <= pos && pos < (uint64_t)tab[2 * np + lo] + tab[np + lo]) {
             } else if (lo + 1 < np && tab[2 * np + lo + 1] == pos && tab[np + lo + 1] != 0) {
                 lo = lo + 1;
             } else {
-                lo = 0;
-                uint32_t hi = np;
-                while (hi - lo > 1) {
-                    uint32_t mid = (lo + hi) >> 1;
-                    if (tab[2 * np + mid] <= pos) lo = mid;
-                    else hi = mid;
-                }
+                lo = search(pos, ra, rb);
             }
             const uint64_t ts = tab[2 * np + lo], hh = tab[np + lo], ms = tab[lo];
             uint64_t end = ts + hh;

@@ -101,13 +101,34 @@ __global__ __launch_bounds__(1024) void k_cwm_starts(uint32_t *tab, uint32_t L)
 __global__ __launch_bounds__(256) void k_cgather(wt_levels src, wt_levels dst, const uint32_t *tab,
                                                  uint32_t l)
 {
-    const uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ uint32_t bnd[2];
     const uint64_t W = dst.words_per_level;
-    if (w >= W) return;
     const uint64_t n = dst.n;
     const uint32_t np = 1u << l;
     const uint32_t *ms = tab + ctab_off(l), *len = ms + np, *ws = len + np;
     const bool to_wt = (dst.kind == WT_TREE);
+    // start of the interval of rank r in dst order
+    auto start = [&](uint32_t r) -> uint64_t { return to_wt ? ws[r] : ms[rev_bits(r, l)]; };
+    // the last interval (in dst order) in [a, b) starting at or before pos
+    // (start(a) <= pos); an empty interval shares its start with the next
+    // one, so it is never the last such interval
+    auto search = [&](uint64_t pos, uint32_t a, uint32_t b) -> uint32_t {
+        while (b - a > 1) {
+            const uint32_t mid = (a + b) >> 1;
+            if (start(mid) <= pos) a = mid;
+            else b = mid;
+        }
+        return a;
+    };
+    // the block's words lie between the intervals of its first and last
+    // positions: one full search each, then every thread searches between
+    const uint64_t w0 = (uint64_t)blockIdx.x * blockDim.x;
+    const uint64_t p_first = w0 << 6;
+    const uint64_t p_last = min(min(w0 + blockDim.x, W) << 6, n) - 1;  // used only when p_first < n
+    if (threadIdx.x < 2 && p_first < n) bnd[threadIdx.x] = search(threadIdx.x ? p_last : p_first, 0, np);
+    __syncthreads();
+    const uint64_t w = w0 + threadIdx.x;
+    if (w >= W) return;
     const uint64_t *sb = src.bits + (uint64_t)l * src.words_per_level;
     const uint64_t ws0 = w << 6;
     const uint64_t we = min(ws0 + 64, n);
@@ -115,22 +136,13 @@ __global__ __launch_bounds__(256) void k_cgather(wt_levels src, wt_levels dst, c
     uint64_t pos = ws0;
     uint32_t lo = np;  // rank (in dst order) of the previous piece's interval
     while (pos < we) {
-        // the last interval (in dst order) starting at or before pos; an
-        // empty interval shares its start with the next one, so it is never
-        // the last such interval.  The next interval in dst order is taken
-        // directly when it starts at pos and is not empty.
+        // the next interval in dst order when it starts at pos and is not
+        // empty, else a search between the block's bounds
         const uint32_t pn = to_wt ? lo + 1 : rev_bits(lo + 1, l);
         if (lo + 1 < np && (to_wt ? ws[pn] : ms[pn]) == pos && len[pn] != 0) {
             lo = lo + 1;
         } else {
-            lo = 0;
-            uint32_t hi = np;
-            while (hi - lo > 1) {
-                const uint32_t mid = (lo + hi) >> 1;
-                const uint32_t p = to_wt ? mid : rev_bits(mid, l);
-                if ((to_wt ? ws[p] : ms[p]) <= pos) lo = mid;
-                else hi = mid;
-            }
+            lo = search(pos, bnd[0], bnd[1] + 1);
         }
         const uint32_t p = to_wt ? lo : rev_bits(lo, l);
         const uint64_t ds = to_wt ? ws[p] : ms[p];
