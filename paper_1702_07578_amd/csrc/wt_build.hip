@@ -439,19 +439,27 @@ __global__ __launch_bounds__(256) void k_gather(const TextDesc *__restrict__ des
         return a;
     };
     // slot 0: the block's first item, slot 1: its last (the same thread when
-    // the block holds one item); positions past the text end clamp to n - 1
+    // the block holds one item)
     for (uint32_t slot = 0; slot < 2; slot++) {
         if (item != (slot ? last : first)) continue;
         b_ti[slot] = ok ? ti : 0xFFFFFFFFu;
         b_l[slot] = l;
-        const uint64_t p0 = (w0 << 6) + (slot ? kGatherWords * 64 - 1 : 0);
-        b_p[slot] = ok ? search(min(p0, dp->n - 1), 0, np) : 0u;
     }
+    __syncthreads();
+    // one text and level for the whole block: the two ends are searched once
+    // (positions past the text end clamp to n - 1)
+    const bool one = b_ti[0] != 0xFFFFFFFFu && b_ti[0] == b_ti[1] && b_l[0] == b_l[1];
+    if (one)
+        for (uint32_t slot = 0; slot < 2; slot++) {
+            if (item != (slot ? last : first)) continue;
+            const uint64_t p0 = (w0 << 6) + (slot ? kGatherWords * 64 - 1 : 0);
+            b_p[slot] = search(min(p0, dp->n - 1), 0, np);
+        }
     __syncthreads();
     if (!ok) return;
     const TextDesc &d = *dp;
     uint32_t ra = 0, rb = np;  // search range of the first piece of a word
-    if (b_ti[0] == ti && b_ti[1] == ti && b_l[0] == l && b_l[1] == l) {
+    if (one) {
         ra = b_p[0];
         rb = b_p[1] + 1;
     }
