@@ -367,9 +367,10 @@ __global__ __launch_bounds__(256) void k_walk(const TextDesc *__restrict__ descs
                                               const uint32_t *__restrict__ bases, uint32_t nd,
                                               uint32_t nitems, uint32_t step)
 {
+    __shared__ uint32_t ends[2];
     const uint32_t item = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t ti = find_text_block(bases, nd, nitems, ends);
     if (item >= nitems) return;
-    const uint32_t ti = find_text(bases, nd, item);
     const TextDesc &d = descs[ti];
     const uint32_t p = item - item_base(bases, nd, ti);
     const uint32_t l = d.K + step;
@@ -406,17 +407,16 @@ __global__ __launch_bounds__(256) void k_gather(const TextDesc *__restrict__ des
     // the intervals of the first and the last word of the block (when they
     // belong to the same text and level, every word of the block between
     // them lies in an interval between theirs)
-    __shared__ uint32_t b_ti[2], b_l[2], b_p[2];
+    __shared__ uint32_t b_ti[2], b_l[2], b_p[2], ends[2];
     const uint32_t first = blockIdx.x * blockDim.x;
     const uint32_t item = first + threadIdx.x;
     const uint32_t last = min(nitems, first + blockDim.x) - 1;
     bool ok = item < nitems;
-    uint32_t ti = 0, l = 0, np = 1;
+    uint32_t ti = find_text_block(bases, nd, nitems, ends), l = 0, np = 1;
     uint64_t w0 = 0;
     const TextDesc *dp = nullptr;
     const uint32_t *tab = nullptr;
     if (ok) {
-        ti = find_text(bases, nd, item);
         dp = &descs[ti];
         const uint64_t idx = item - item_base(bases, nd, ti);
         ok = dp->kind == WT_TREE && dp->G > 1;

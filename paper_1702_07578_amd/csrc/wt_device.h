@@ -21,6 +21,36 @@ __device__ inline uint32_t find_text(const uint32_t *__restrict__ bases, uint32_
     return lo;
 }
 
+// The same among texts [a, b] (bases[a] <= item): for a workgroup whose
+// items are known to lie in the texts of its first and last item.
+__device__ inline uint32_t find_text_in(const uint32_t *__restrict__ bases, uint32_t a, uint32_t b,
+                                        uint32_t item)
+{
+    uint32_t lo = a, hi = b + 1;
+    while (hi - lo > 1) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (bases[mid] <= item) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Text of a workgroup's item, with the texts of the group's first and last
+// items found once (by threads 0 and 1) and shared through `ends`; every
+// thread of the group must call it.
+__device__ inline uint32_t find_text_block(const uint32_t *__restrict__ bases, uint32_t nd, uint32_t nitems,
+                                           uint32_t *ends)
+{
+    const uint32_t first = blockIdx.x * blockDim.x;
+    const uint32_t last = min(nitems, first + blockDim.x) - 1;
+    if (nd == 1) return 0;
+    if (threadIdx.x < 2) ends[threadIdx.x] = find_text(bases, nd, threadIdx.x ? last : first);
+    __syncthreads();
+    const uint32_t item = first + threadIdx.x;
+    if (item >= nitems) return 0;
+    return ends[0] == ends[1] ? ends[0] : find_text_in(bases, ends[0], ends[1], item);
+}
+
 __device__ inline uint32_t item_base(const uint32_t *__restrict__ bases, uint32_t nd, uint32_t text)
 {
     return nd == 1 ? 0u : bases[text];
