@@ -315,36 +315,36 @@ __device__ __attribute__((always_inline)) inline void split_pass(uint32_t (&v)[k
                                                                  WaveSmem<E, REORDER, PAIR, KB> &sm)
 {
     const uint32_t lane = lane_id();
-    uint32_t neg_lane = 0u - lane;
+    constexpr uint32_t e = sizeof(E);
     // LDS address of the element buffer
     const uint32_t ebase = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) E *)sm.elem;
     uint32_t acc_lo = 0, acc_hi = 0;
-    uint32_t base0 = 0;
     base1 = __builtin_amdgcn_readfirstlane(base1);
+    // In chunk c a one goes to base1_c + (ones before the lane) and a zero to
+    // base0_c + (zeros before the lane), with base0_c + base1_c = base1 + 64 c:
+    // the two destinations of a lane add up to Q + 64 c (in bytes, times e).
+    // Both are taken 32 c e below their place, which the store's immediate
+    // offset adds back, so the zero's place is Q minus the one's.
+    const uint32_t Q = 2u * ebase + (base1 + lane) * e;
+    uint32_t t1 = ebase + base1 * e;  // the ones' base of chunk c, minus 32 c e
     static_for<0, kChunks>([&](auto ci) {
         constexpr uint32_t c = decltype(ci)::value;
-        // keeps each chunk's ranks from being computed ahead of time (which
-        // would hold one register per chunk)
-        asm volatile("" : "+v"(neg_lane));
         const uint32_t x = v[c];
         const bool one = (x & bit) != 0;
         const uint64_t B = __ballot(one);
         put_lane<c>(acc_lo, acc_hi, B);
         if (SPLIT) {
-            // m = (ones before this lane in the chunk) - lane; a one goes to
-            // base1 + m + lane, a zero to base0 - m.  The bases are kept
-            // opaque so that they stay scalar.
-            const uint32_t m = __builtin_amdgcn_mbcnt_hi(
-                (uint32_t)(B >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)B, neg_lane));
-            const uint32_t s0 = ebase + base0 * (uint32_t)sizeof(E);
-            const uint32_t s1 = ebase + base1 * (uint32_t)sizeof(E);
-            const uint32_t i1 = s1 + (m + lane) * (uint32_t)sizeof(E);
-            const uint32_t i0 = s0 - m * (uint32_t)sizeof(E);
-            *(__attribute__((address_space(3))) E *)(uintptr_t)(one ? i1 : i0) = (E)x;
-            const uint32_t ones = __popcll(B);
-            base0 += 64u - ones;
-            base1 += ones;
-            asm volatile("" : "+s"(base0), "+s"(base1));
+            uint32_t i1;
+            if (e == 1)
+                i1 = __builtin_amdgcn_mbcnt_hi((uint32_t)(B >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)B, t1));
+            else
+                i1 = t1 + __builtin_amdgcn_mbcnt_hi((uint32_t)(B >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)B, 0u)) * e;
+            const uint32_t i0 = Q - i1;
+            *(__attribute__((address_space(3))) E *)(uintptr_t)((one ? i1 : i0) + 32u * c * e) = (E)x;
+            t1 += __popcll(B) * e - 32u * e;
+            // opaque, so that it stays scalar and each chunk's ranks are not
+            // computed ahead of time (one register per chunk)
+            asm volatile("" : "+s"(t1));
         }
     });
     if (lane < kChunks) sm.bits[a][lane] = ((uint64_t)acc_hi << 32) | acc_lo;
@@ -564,8 +564,15 @@ __device__ void wave_range(const TextDesc &d, uint32_t g, uint32_t Kg, uint32_t 
 // Work item = (text, range); wave w of workgroup b takes items
 // b * kScatWaves + w, then strides by the whole grid.  The REORDER variant
 // takes the texts whose symbols move on to another group after group g.
+// Waves per SIMD the registers are held to.  The byte-symbol pair kernel
+// with 7-level tables fits five workgroups per CU in LDS; at five waves its
+// registers spill only values used by a padded last tile.  The others keep
+// the compiler's choice (their LDS holds at most four).
 template <typename E, bool REORDER, bool PAIR, uint32_t KB>
-__global__ __launch_bounds__(kScatWaves * 64) void k_scatter(const TextDesc *__restrict__ descs,
+constexpr uint32_t kScatMinWaves = (sizeof(E) == 1 && PAIR && !REORDER && KB == 7) ? 5 : 1;
+
+template <typename E, bool REORDER, bool PAIR, uint32_t KB>
+__global__ __launch_bounds__(kScatWaves * 64) __attribute__((amdgpu_waves_per_eu(kScatMinWaves<E, REORDER, PAIR, KB>))) void k_scatter(const TextDesc *__restrict__ descs,
                                                              const uint32_t *__restrict__ bases,
                                                              uint32_t nd, uint32_t nitems, uint32_t g)
 {
