@@ -60,6 +60,26 @@ def scatter_traffic(per_launch_alg_bytes, path=COUNTERS):
     return c.get("bytes_per_launch")
 
 
+def valu_limiter(path, what, avg_ms):
+    """The scatter's limiter from the committed instruction counters: VALU
+    instructions per 64 symbols and, at this run's launch time, the share of
+    the chip's VALU issue rate they take (1024 SIMDs at 2.4 GHz, one wave64
+    instruction per SIMD every 4 cycles).  Counters taken on another version
+    of the kernel source are not used."""
+    if os.path.exists(path):
+        c = json.load(open(path))
+        src = hashlib.sha256(open(SCATTER_SRC, "rb").read()).hexdigest()
+        if c.get("source_sha256") == src and "sq" in c:
+            sq = c["sq"]
+            valu = sq["per_dispatch_median"]["SQ_INSTS_VALU"]
+            issue = 1024 * 2.4e9 / 4
+            frac = valu / (avg_ms / 1e3 * issue)
+            return (f"vector-instruction issue: about {sq['valu_per_64_symbols']:.0f} VALU instructions per 64 "
+                    f"symbols for {what} (rocprofv3 SQ_INSTS_VALU), about {100 * frac:.0f}% of the chip's VALU "
+                    f"issue rate (1024 SIMDs x 2.4 GHz / 4 cycles per wave64 instruction)")
+    return "vector-instruction issue (instruction counters not taken on this kernel source)"
+
+
 def cpu_baseline(text, L, sample_n):
     import oracle
     orc = oracle.load()
@@ -413,9 +433,7 @@ def main():
     achieved = per_launch_bytes / (scat["avg_ms"] / 1e3) / 1e9
     default_markov = args.workload == "markov96" and not args.n
     roofline = {"kernel": "scatter", "bound": "hbm",
-                "limiter": ("vector-instruction issue: about 79 VALU instructions per 64 symbols "
-                            "for 7 levels (rocprofv3 SQ_INSTS_VALU), about 78% of the chip's issue rate"
-                            if default_markov else
+                "limiter": (valu_limiter(COUNTERS, "7 levels", scat["avg_ms"]) if default_markov else
                             "vector-instruction issue (counters taken on markov96 only)"),
                 "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -453,9 +471,8 @@ def main():
         pair = {"ms_per_step": pair_ms, "value": 2 * n / (pair_ms / 1e3), "kernels": pk,
                 "roofline": {"kernel": ("scatter (pair: WT and WM runs from one set of splits)" if L <= 8 else
                                         "scatter (the WM's groups; the WT is gathered from the WM)"), "bound": "hbm",
-                             "limiter": ("vector-instruction issue: about 92 VALU instructions per 64 symbols for "
-                                         "7 levels of both structures (rocprofv3 SQ_INSTS_VALU), about 74% of the "
-                                         "chip's issue rate at 4 waves per SIMD" if default_markov and L <= 8 else
+                             "limiter": (valu_limiter(PAIR_COUNTERS, "7 levels of both structures",
+                                                      pk["scatter"]["avg_ms"]) if default_markov and L <= 8 else
                                          "vector-instruction issue (counters taken on markov96 only)"),
                              "achieved": round(pach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": round(pach / HBM_PEAK_GBS, 4),
