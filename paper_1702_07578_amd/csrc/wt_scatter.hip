@@ -566,20 +566,32 @@ __device__ void wave_range(const TextDesc &d, uint32_t g, uint32_t Kg, uint32_t 
 // takes the texts whose symbols move on to another group after group g.
 // Waves per SIMD the registers are held to.  The byte-symbol pair kernel
 // with 7-level tables fits five workgroups per CU in LDS; at five waves its
-// registers spill only values used by a padded last tile.  The others keep
-// the compiler's choice (their LDS holds at most four).
+// registers spill only values used by a padded last tile.  The pair kernel
+// that also re-orders (13.5 KiB of LDS per wave for byte symbols, 15.5 KiB
+// for 16-bit ones) runs single-wave workgroups, ten or eleven per CU instead
+// of eight in 4-wave workgroups; its registers are held to three waves per
+// SIMD.  The others keep the compiler's choice (their LDS holds at most four
+// waves per SIMD).
 template <typename E, bool REORDER, bool PAIR, uint32_t KB>
-constexpr uint32_t kScatMinWaves = (sizeof(E) == 1 && PAIR && !REORDER && KB == 7) ? 5 : 1;
+constexpr uint32_t kScatMinWaves = (sizeof(E) == 1 && PAIR && !REORDER && KB == 7) ? 5
+                                   : (PAIR && REORDER && sizeof(E) <= 2)          ? 3
+                                                                                  : 1;
+// waves per workgroup (LDS is granted per workgroup)
+template <bool REORDER, bool PAIR>
+constexpr uint32_t kScatBlockWaves = (PAIR && REORDER) ? 1 : kScatWaves;
 
+// Work item = (text, range); wave w of workgroup b takes items
+// b * waves + w, then strides by the whole grid.  The REORDER variant
+// takes the texts whose symbols move on to another group after group g.
 template <typename E, bool REORDER, bool PAIR, uint32_t KB>
-__global__ __launch_bounds__(kScatWaves * 64) __attribute__((amdgpu_waves_per_eu(kScatMinWaves<E, REORDER, PAIR, KB>))) void k_scatter(const TextDesc *__restrict__ descs,
+__global__ __launch_bounds__((kScatBlockWaves<REORDER, PAIR> * 64)) __attribute__((amdgpu_waves_per_eu(kScatMinWaves<E, REORDER, PAIR, KB>))) void k_scatter(const TextDesc *__restrict__ descs,
                                                              const uint32_t *__restrict__ bases,
                                                              uint32_t nd, uint32_t nitems, uint32_t g)
 {
-    __shared__ WaveSmem<E, REORDER, PAIR, KB> sm[kScatWaves];
-    const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    for (uint32_t item = blockIdx.x * kScatWaves + w; item < nitems;
-         item += gridDim.x * kScatWaves) {
+    constexpr uint32_t BW = kScatBlockWaves<REORDER, PAIR>;
+    __shared__ WaveSmem<E, REORDER, PAIR, KB> sm[BW];
+    const uint32_t w = BW == 1 ? 0u : __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (uint32_t item = blockIdx.x * BW + w; item < nitems; item += gridDim.x * BW) {
         const uint32_t ti = find_text(bases, nd, item);
         const TextDesc &d = descs[ti];
         const uint32_t r = item - item_base(bases, nd, ti);
@@ -592,38 +604,37 @@ __global__ __launch_bounds__(kScatWaves * 64) __attribute__((amdgpu_waves_per_eu
     }
 }
 
-template <typename E>
-static void launch_width(const TextDesc *d_descs, const GroupLaunch &gl, uint32_t grid,
-                         const LaunchCtx &ctx)
+// one instantiation over all items: one wave per item, or a grid capped at
+// grid_cap workgroups of kScatWaves waves (the same number of waves)
+template <typename E, bool REORDER, bool PAIR, uint32_t KB>
+static void launch_one(const TextDesc *d_descs, const GroupLaunch &gl, const LaunchCtx &ctx)
 {
-    const dim3 block(kScatWaves * 64);
+    constexpr uint32_t BW = kScatBlockWaves<REORDER, PAIR>;
+    uint32_t grid = (gl.nranges + BW - 1) / BW;
+    const uint32_t cap = gl.grid_cap * (kScatWaves / BW);
+    if (cap && grid > cap) grid = cap;
+    hipLaunchKernelGGL((k_scatter<E, REORDER, PAIR, KB>), dim3(grid), dim3(BW * 64), 0, ctx.stream, d_descs,
+                       gl.range_bases, gl.nd, gl.nranges, gl.g);
+}
+
+template <typename E>
+static void launch_width(const TextDesc *d_descs, const GroupLaunch &gl, const LaunchCtx &ctx)
+{
     constexpr uint32_t K8 = kMaxGroupBits;
     // pairs: WT and WM of one text (one group) from the same splits
-    if (gl.g == 0 && (gl.pmask & 2u))
-        hipLaunchKernelGGL((k_scatter<E, false, true, 7>), dim3(grid), block, 0, ctx.stream, d_descs,
-                           gl.range_bases, gl.nd, gl.nranges, gl.g);
-    if (gl.g == 0 && (gl.pmask & 4u))
-        hipLaunchKernelGGL((k_scatter<E, false, true, K8>), dim3(grid), block, 0, ctx.stream, d_descs,
-                           gl.range_bases, gl.nd, gl.nranges, gl.g);
-    if (gl.g == 0 && (gl.pmask & 8u))
-        hipLaunchKernelGGL((k_scatter<E, true, true, K8>), dim3(grid), block, 0, ctx.stream, d_descs,
-                           gl.range_bases, gl.nd, gl.nranges, gl.g);
+    if (gl.g == 0 && (gl.pmask & 2u)) launch_one<E, false, true, 7>(d_descs, gl, ctx);
+    if (gl.g == 0 && (gl.pmask & 4u)) launch_one<E, false, true, K8>(d_descs, gl, ctx);
+    if (gl.g == 0 && (gl.pmask & 8u)) launch_one<E, true, true, K8>(d_descs, gl, ctx);
     if (!(gl.pmask & 1u)) return;
-    if (gl.rmask & 1u)
-        hipLaunchKernelGGL((k_scatter<E, false, false, K8>), dim3(grid), block, 0, ctx.stream, d_descs,
-                           gl.range_bases, gl.nd, gl.nranges, gl.g);
-    if (gl.rmask & 2u)
-        hipLaunchKernelGGL((k_scatter<E, true, false, K8>), dim3(grid), block, 0, ctx.stream, d_descs,
-                           gl.range_bases, gl.nd, gl.nranges, gl.g);
+    if (gl.rmask & 1u) launch_one<E, false, false, K8>(d_descs, gl, ctx);
+    if (gl.rmask & 2u) launch_one<E, true, false, K8>(d_descs, gl, ctx);
 }
 
 hipError_t launch_scatter(const TextDesc *d_descs, const GroupLaunch &gl, const LaunchCtx &ctx)
 {
-    uint32_t grid = (gl.nranges + kScatWaves - 1) / kScatWaves;
-    if (gl.grid_cap && grid > gl.grid_cap) grid = gl.grid_cap;
-    if (gl.bmask & 1u) launch_width<uint8_t>(d_descs, gl, grid, ctx);
-    if (gl.bmask & 2u) launch_width<uint16_t>(d_descs, gl, grid, ctx);
-    if (gl.bmask & 4u) launch_width<uint32_t>(d_descs, gl, grid, ctx);
+    if (gl.bmask & 1u) launch_width<uint8_t>(d_descs, gl, ctx);
+    if (gl.bmask & 2u) launch_width<uint16_t>(d_descs, gl, ctx);
+    if (gl.bmask & 4u) launch_width<uint32_t>(d_descs, gl, ctx);
     if (ctx.after) ctx.after(ctx.user, KID_SCATTER);
     return hipGetLastError();
 }
