@@ -17,7 +17,6 @@ constexpr uint32_t kTileWaves = kTileThreads / 64;
 // The scatter gives every wave a range of its own and walks it one tile at a
 // time; a tile is at most kWaveTile symbols (held in registers, 32 per lane).
 constexpr uint32_t kWaveTile = 2048;
-constexpr uint32_t kScatWaves = 4;  // waves per scatter workgroup
 // Largest number of levels handled by one pass over the (re-ordered) text.
 constexpr uint32_t kMaxGroupBits = 8;
 // Ranges per text when the text is long enough: four per resident scatter

@@ -561,34 +561,38 @@ __device__ void wave_range(const TextDesc &d, uint32_t g, uint32_t Kg, uint32_t 
     wave_sync();
 }
 
-// Work item = (text, range); wave w of workgroup b takes items
-// b * kScatWaves + w, then strides by the whole grid.  The REORDER variant
-// takes the texts whose symbols move on to another group after group g.
-// Waves per SIMD the registers are held to.  The byte-symbol pair kernel
-// with 7-level tables fits five workgroups per CU in LDS; at five waves its
-// registers spill only values used by a padded last tile.  The pair kernel
-// that also re-orders (13.5 KiB of LDS per wave for byte symbols, 15.5 KiB
-// for 16-bit ones) runs single-wave workgroups, ten or eleven per CU instead
-// of eight in 4-wave workgroups; its registers are held to three waves per
-// SIMD.  The others keep the compiler's choice (their LDS holds at most four
-// waves per SIMD).
+// Waves per scatter workgroup.  LDS is granted per workgroup: groups of
+// four waves keep neighbouring ranges on one CU and its SIMDs evenly loaded,
+// but when single waves pack a CU's 160 KiB markedly tighter (by a quarter or
+// more: eleven instead of eight waves of the 13.5 KiB re-ordering pair
+// kernel, for instance) each workgroup is one wave.
+constexpr uint32_t kCuLdsBytes = 160 * 1024;
+template <typename E, bool REORDER, bool PAIR, uint32_t KB>
+constexpr uint32_t scat_block_waves()
+{
+    constexpr uint32_t S = sizeof(WaveSmem<E, REORDER, PAIR, KB>);
+    constexpr uint32_t w4 = 4 * (kCuLdsBytes / (4 * S)), w1 = kCuLdsBytes / S;
+    return (4 * w1 >= 5 * w4) ? 1u : 4u;
+}
+
+// Waves per SIMD the registers are held to: the byte-symbol pair kernel with
+// 7-level tables (7.5 KiB of LDS) to five, where only values used by a padded
+// last tile spill; the re-ordering pair kernel of 1- and 2-byte symbols to
+// three.  The others keep the compiler's choice.
 template <typename E, bool REORDER, bool PAIR, uint32_t KB>
 constexpr uint32_t kScatMinWaves = (sizeof(E) == 1 && PAIR && !REORDER && KB == 7) ? 5
                                    : (PAIR && REORDER && sizeof(E) <= 2)          ? 3
                                                                                   : 1;
-// waves per workgroup (LDS is granted per workgroup)
-template <bool REORDER, bool PAIR>
-constexpr uint32_t kScatBlockWaves = (PAIR && REORDER) ? 1 : kScatWaves;
 
-// Work item = (text, range); wave w of workgroup b takes items
-// b * waves + w, then strides by the whole grid.  The REORDER variant
-// takes the texts whose symbols move on to another group after group g.
+// Work item = (text, range); wave w of workgroup b takes item b BW + w,
+// then strides by the whole grid.  The REORDER variant takes the texts whose
+// symbols move on to another group after group g.
 template <typename E, bool REORDER, bool PAIR, uint32_t KB>
-__global__ __launch_bounds__((kScatBlockWaves<REORDER, PAIR> * 64)) __attribute__((amdgpu_waves_per_eu(kScatMinWaves<E, REORDER, PAIR, KB>))) void k_scatter(const TextDesc *__restrict__ descs,
+__global__ __launch_bounds__((scat_block_waves<E, REORDER, PAIR, KB>() * 64)) __attribute__((amdgpu_waves_per_eu(kScatMinWaves<E, REORDER, PAIR, KB>))) void k_scatter(const TextDesc *__restrict__ descs,
                                                              const uint32_t *__restrict__ bases,
                                                              uint32_t nd, uint32_t nitems, uint32_t g)
 {
-    constexpr uint32_t BW = kScatBlockWaves<REORDER, PAIR>;
+    constexpr uint32_t BW = scat_block_waves<E, REORDER, PAIR, KB>();
     __shared__ WaveSmem<E, REORDER, PAIR, KB> sm[BW];
     const uint32_t w = BW == 1 ? 0u : __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (uint32_t item = blockIdx.x * BW + w; item < nitems; item += gridDim.x * BW) {
@@ -604,14 +608,15 @@ __global__ __launch_bounds__((kScatBlockWaves<REORDER, PAIR> * 64)) __attribute_
     }
 }
 
-// one instantiation over all items: one wave per item, or a grid capped at
-// grid_cap workgroups of kScatWaves waves (the same number of waves)
+// one instantiation over all items: one wave per item, or, with a cap, a
+// persistent grid of grid_cap workgroups of four waves (the same number of
+// waves whatever the instantiation's workgroup size)
 template <typename E, bool REORDER, bool PAIR, uint32_t KB>
 static void launch_one(const TextDesc *d_descs, const GroupLaunch &gl, const LaunchCtx &ctx)
 {
-    constexpr uint32_t BW = kScatBlockWaves<REORDER, PAIR>;
+    constexpr uint32_t BW = scat_block_waves<E, REORDER, PAIR, KB>();
     uint32_t grid = (gl.nranges + BW - 1) / BW;
-    const uint32_t cap = gl.grid_cap * (kScatWaves / BW);
+    const uint32_t cap = gl.grid_cap * (4 / BW);
     if (cap && grid > cap) grid = cap;
     hipLaunchKernelGGL((k_scatter<E, REORDER, PAIR, KB>), dim3(grid), dim3(BW * 64), 0, ctx.stream, d_descs,
                        gl.range_bases, gl.nd, gl.nranges, gl.g);
