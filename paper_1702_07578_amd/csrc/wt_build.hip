@@ -477,6 +477,17 @@ __global__ __launch_bounds__(256) void k_gather(const TextDesc *__restrict__ des
             if (lo < np && tab[2 * np + lo] <= pos && pos < (uint64_t)tab[2 * np + lo] + tab[np + lo]) {
             } else if (lo + 1 < np && tab[2 * np + lo + 1] == pos && tab[np + lo + 1] != 0) {
                 lo = lo + 1;
+            } else if (lo < np) {
+                // empty intervals follow the previous one: a bracket that
+                // doubles from it until an interval starts past pos, then a
+                // search inside it (log of the gap, not of the range)
+                uint32_t a = lo, b = lo + 1, step = 1;
+                while (b < rb && tab[2 * np + b] <= pos) {
+                    a = b;
+                    step <<= 1;
+                    b = a + step;
+                }
+                lo = search(pos, a, max(min(b, rb), a + 1));  // never empty
             } else {
                 lo = search(pos, ra, rb);
             }

@@ -141,6 +141,18 @@ __global__ __launch_bounds__(256) void k_cgather(wt_levels src, wt_levels dst, c
         const uint32_t pn = to_wt ? lo + 1 : rev_bits(lo + 1, l);
         if (lo + 1 < np && (to_wt ? ws[pn] : ms[pn]) == pos && len[pn] != 0) {
             lo = lo + 1;
+        } else if (lo < np) {
+            // empty intervals follow the previous one: a bracket that
+            // doubles from it until an interval starts past pos, then a
+            // search inside it
+            const uint32_t hi = bnd[1] + 1;
+            uint32_t a = lo, b = lo + 1, step = 1;
+            while (b < hi && start(b) <= pos) {
+                a = b;
+                step <<= 1;
+                b = a + step;
+            }
+            lo = search(pos, a, max(min(b, hi), a + 1));  // never empty
         } else {
             lo = search(pos, bnd[0], bnd[1] + 1);
         }
