@@ -347,15 +347,32 @@ __global__ __launch_bounds__(256) void k_mgather(const wt_levels *__restrict__ p
         if (next) {
             lo = lo + 1;
         } else {
-            lo = 0;
-            uint64_t hi = ne;
-            while (hi - lo > 1) {
-                const uint64_t mid = (lo + hi) >> 1;
-                const uint32_t k = (uint32_t)(mid / count), c = (uint32_t)(mid % count);
+            // start (in the whole) of the interval at position m of its order
+            auto start_at = [&](uint64_t m) -> uint64_t {
+                const uint32_t k = (uint32_t)(m / count), c = (uint32_t)(m % count);
                 const uint32_t p = wt ? k : rev_bits(k, l);
-                if (ds[(uint64_t)p * count + c] <= pos) lo = mid;
+                return ds[(uint64_t)p * count + c];
+            };
+            uint64_t a = 0, hi = ne;
+            if (lo < ne) {
+                // after a piece: a bracket that doubles from its interval
+                // until an interval starts past pos (empty intervals between)
+                uint64_t step = 1;
+                a = lo;
+                hi = lo + 1;
+                while (hi < ne && start_at(hi) <= pos) {
+                    a = hi;
+                    step <<= 1;
+                    hi = a + step;
+                }
+                if (hi > ne) hi = ne;
+            }
+            while (hi - a > 1) {
+                const uint64_t mid = (a + hi) >> 1;
+                if (start_at(mid) <= pos) a = mid;
                 else hi = mid;
             }
+            lo = a;
         }
         const uint32_t k = (uint32_t)(lo / count), c = (uint32_t)(lo % count);
         const uint32_t p = wt ? k : rev_bits(k, l);
