@@ -382,12 +382,14 @@ def main():
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
 
+    spans = []  # (kind, first, last) recorded launches of every timed build
+
     def step(rec=None):
         for k in (B.WT_TREE, B.WT_MATRIX):
             if rec is None:
                 B.build(d_text, n, b, L, k, tune=tune, ws=ws, out=structs[k])
             else:
-                rec.build(d_text, n, b, L, k, structs[k], ws, tune=tune)
+                spans.append((k,) + rec.build(d_text, n, b, L, k, structs[k], ws, tune=tune))
 
     for _ in range(args.warmup):
         step()
@@ -407,6 +409,7 @@ def main():
     rec = B.EventRecorder(per_step * args.steps + 8)
 
     # ---- timed region ----
+    spans.clear()
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -421,6 +424,12 @@ def main():
     ms_per_step = total_ms / args.steps
     value = 2 * n / (ms_per_step / 1e3)
     kt = rec.kernel_times(ev0)
+    # each structure on its own: its launches' durations, each measured from
+    # the event before it (the builds run back to back on one stream)
+    kind_ms = {}
+    for k, first, last in spans:
+        t = sum(sum(v) for v in rec.kernel_times(ev0, first, last).values())
+        kind_ms[k] = kind_ms.get(k, 0.0) + t / args.steps
     kernels = {name: {"launches": len(v), "avg_ms": sum(v) / len(v), "total_ms_per_step": sum(v) / args.steps}
                for name, v in kt.items()}
     dom = max(kernels, key=lambda k: kernels[k]["total_ms_per_step"])
@@ -601,7 +610,9 @@ def main():
     # the headline step: the WT and the WM of the text by the pair build when
     # the levels fit one group (both structures from one pass), else by two
     # builds; the other way is reported beside it
-    separate = {"ms_per_step": round(ms_per_step, 4), "value": round(value, 1), "roofline": roofline,
+    separate = {"ms_per_step": round(ms_per_step, 4), "value": round(value, 1),
+                "wt_build_ms": round(kind_ms.get(B.WT_TREE, float("nan")), 4),
+                "wm_build_ms": round(kind_ms.get(B.WT_MATRIX, float("nan")), 4), "roofline": roofline,
                 "build_alg_gbs": round(build_gbs, 1),
                 "kernels": {k: {"avg_ms": round(v["avg_ms"], 4), "launches_per_step": v["launches"] // args.steps}
                             for k, v in kernels.items()}}
