@@ -38,6 +38,7 @@ struct WaveSmem {
     static constexpr uint32_t kRunsB = (1u << KB) - 1;  // (level, key) pairs of levels 0..KB-1
     static constexpr uint32_t kKeysB = 1u << KB;        // keys of level KB (the finest)
     static constexpr uint32_t kWordsB = KB * kChunks;   // full output words of one tile
+    static constexpr uint32_t kScanPer = (kKeysB + 63) / 64;  // table entries per lane in a scan
     // level a of the tile in order a; while the tables are built (and at a
     // range start) it holds the finest key counts and their prefix sums
     uint64_t bits[KB][kChunks];
@@ -213,7 +214,7 @@ __device__ __attribute__((always_inline)) inline void copy_full_words(const Text
     const uint32_t lane = lane_id();
     const uint32_t nr = lvl_off(Kg);
     const uint32_t *G = sd.G;
-    const uint32_t total = wave_exscan_n<4>(
+    const uint32_t total = wave_exscan_n<WaveSmem<E, REORDER, PAIR, KB>::kScanPer>(
         nr, [&](uint32_t e) { return full_words(G[e], sm.h[e]); },
         [&](uint32_t e, uint32_t x) { sm.co.wb[e] = (uint16_t)x; });
     // run of every word: the run whose first word it is, carried forward
@@ -441,7 +442,7 @@ __device__ __attribute__((always_inline)) inline void wave_tile(const TextDesc &
 
     // 2. the tile's count of every key of levels 0..Kg-1, as differences of
     //    the prefix sums P of the finest counts (padding not counted)
-    wave_exscan_n<4>(
+    wave_exscan_n<WaveSmem<E, REORDER, PAIR, KB>::kScanPer>(
         nk, [&](uint32_t k) { return cnt[k]; }, [&](uint32_t k, uint32_t x) { P[k] = (uint16_t)x; });
     if (lane == 0) P[nk] = (uint16_t)len;
     if (REORDER)
@@ -457,7 +458,7 @@ __device__ __attribute__((always_inline)) inline void wave_tile(const TextDesc &
     //    One scan runs over levels 1..Kg-1 one after the other: each level's
     //    counts add up to len, so level a starts at (a - 1) len.
     if (lane == 0) sm.lo[0] = 0;
-    wave_exscan_n<4>(
+    wave_exscan_n<WaveSmem<E, REORDER, PAIR, KB>::kScanPer>(
         lvl_off(Kg) - 1,
         [&](uint32_t i) {
             const uint32_t a = level_of(i + 1);
@@ -468,7 +469,7 @@ __device__ __attribute__((always_inline)) inline void wave_tile(const TextDesc &
             sm.lo[lvl_off(a) + rev_bits(i + 1 - lvl_off(a), a)] = (uint16_t)(x - (a - 1) * len);
         });
     if (REORDER)
-        wave_exscan_n<4>(
+        wave_exscan_n<WaveSmem<E, REORDER, PAIR, KB>::kScanPer>(
             nk, [&](uint32_t i) { return (uint32_t)sm.hK[rev_bits(i, Kg)]; },
             [&](uint32_t i, uint32_t x) { sm.loK[rev_bits(i, Kg)] = (uint16_t)x; });
     wave_sync();
