@@ -94,7 +94,8 @@ typedef struct wt_tune {
     uint32_t tile_log2;  /* accepted and ignored: a tile is always 2048 symbols (one wave's registers) */
     uint32_t group_bits; /* levels handled per pass over the text, 1..8 */
     uint32_t grid;       /* ranges of consecutive tiles per text, one wave each (0: 12288) */
-    uint32_t persist;    /* workgroups per launch, looping over all work items (0: one per item) */
+    uint32_t persist;    /* workgroups per launch, looping over all work items (0: one per item); the
+                            scatter counts them as groups of 4 waves (persist * 4 waves) */
 } wt_tune;
 
 /* Bytes of the output buffer for a text of length n over lg_sigma levels
