@@ -187,6 +187,64 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def steady_state_small(args, B, n, L, b_alg_build, log):
+    """Many distinct texts of the small configuration back to back: the WT and
+    the WM of each of `count` uniform texts (512 MiB of text in all, more than
+    the 256 MB last-level cache), as one batched build in one graph replay;
+    every structure is checked against its standalone build."""
+    import torch
+
+    from paper_1702_07578_amd import autotune
+    from paper_1702_07578_amd import inputs
+
+    dev = torch.device("cuda:0")
+    count = args.steady_texts
+    texts = [inputs.uniform(n, 256, 1, (1 << 16) + i) for i in range(count)]
+    d_texts = [B.to_device(t, dev) for t in texts]
+    items = [(d, n, 1, L, kind, B.Structure(n, L, kind, device=dev))
+             for d in d_texts for kind in (B.WT_TREE, B.WT_MATRIX)]
+    tune, _ = autotune.tune(items, log=log)
+    batch = B.Batch(items, tune=tune)
+    for it in items:
+        it[5].buf.zero_()
+    batch.prepare()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(graph, stream=side):
+            batch.launch(side)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    ws = torch.empty(max(B.workspace_bytes(n, 1, L, k) for k in (B.WT_TREE, B.WT_MATRIX)), dtype=torch.uint8,
+                     device=dev)
+    alone = {k: B.Structure(n, L, k, device=dev) for k in (B.WT_TREE, B.WT_MATRIX)}
+    for d, _, _, _, kind, s in items:
+        if s.status() != 0:
+            raise SystemExit("steady-state batch reported an error status")
+        alone[kind].buf.zero_()
+        B.build(d, n, 1, L, kind, ws=ws, out=alone[kind])
+        if not torch.equal(s.buf, alone[kind].buf):
+            raise SystemExit("steady-state batch output differs from the standalone build")
+    alg = 2 * count * b_alg_build
+    return {"texts": count, "symbols": count * n, "text_bytes": count * n,
+            "build": "WT and WM of every text, one batched build, one graph replay",
+            "tune": {"grid": tune.grid if tune else 0, "persist": tune.persist if tune else 0},
+            "ms": round(ms, 4), "symbols_per_s": round(2 * count * n / (ms / 1e3), 1),
+            "alg_bytes": int(alg), "alg_gbs": round(alg / (ms / 1e3) / 1e9, 1),
+            "frac": round(alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def run_serve(args):
     """Serving workload: Poisson arrivals of build requests (texts resident
     in HBM, lengths floor(2^U(12,26)), sigma in {256, 2^16}) mixed with query
@@ -334,6 +392,8 @@ def main():
                     help="first run a plain elementwise copy of 1 GiB three times (the reference "
                          "kernel for scaling the HBM byte counters)")
     ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--steady-texts", type=int, default=512,
+                    help="uniform256: distinct texts of the steady-state measurement (0: skip)")
     ap.add_argument("--tune-cache", default="", help="JSON cache of the batch autotuner")
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--pool", type=int, default=64)
@@ -654,6 +714,10 @@ def main():
         "sort_strategy": ps_ms,
         "separate_builds": separate if pair is not None else None,
     }
+    if args.workload == "uniform256" and not args.n and args.steady_texts:
+        # the small configuration: its step above is the isolated latency; this
+        # is the steady-state rate of many such texts
+        out["steady_state"] = steady_state_small(args, B, n, L, b_alg_build, log)
     print(json.dumps(out), flush=True)
 
 
