@@ -408,6 +408,7 @@ __global__ __launch_bounds__(256) void k_gather(const TextDesc *__restrict__ des
     // belong to the same text and level, every word of the block between
     // them lies in an interval between theirs)
     __shared__ uint32_t b_ti[2], b_l[2], b_p[2], ends[2];
+    __shared__ uint64_t b_pos[2];
     const uint32_t first = blockIdx.x * blockDim.x;
     const uint32_t item = first + threadIdx.x;
     const uint32_t last = min(nitems, first + blockDim.x) - 1;
@@ -444,17 +445,21 @@ __global__ __launch_bounds__(256) void k_gather(const TextDesc *__restrict__ des
         if (item != (slot ? last : first)) continue;
         b_ti[slot] = ok ? ti : 0xFFFFFFFFu;
         b_l[slot] = l;
+        b_pos[slot] = (w0 << 6) + (slot ? kGatherWords * 64 - 1 : 0);
     }
     __syncthreads();
-    // one text and level for the whole block: the two ends are searched once
-    // (positions past the text end clamp to n - 1)
+    // one text and level for the whole block: the two ends are searched once,
+    // by wave 0 and wave 1 (positions past the text end clamp to n - 1)
     const bool one = b_ti[0] != 0xFFFFFFFFu && b_ti[0] == b_ti[1] && b_l[0] == b_l[1];
-    if (one)
-        for (uint32_t slot = 0; slot < 2; slot++) {
-            if (item != (slot ? last : first)) continue;
-            const uint64_t p0 = (w0 << 6) + (slot ? kGatherWords * 64 - 1 : 0);
-            b_p[slot] = search(min(p0, dp->n - 1), 0, np);
-        }
+    if (one && threadIdx.x < 128) {
+        const uint32_t slot = threadIdx.x >> 6;
+        const TextDesc &d0 = descs[b_ti[0]];
+        const uint32_t np0 = 1u << b_l[0];
+        const uint32_t *tab0 = d0.walk + walk_off(d0.K, b_l[0]);
+        const uint64_t r = wave_search_last_le(np0, min(b_pos[slot], d0.n - 1),
+                                               [&](uint64_t p) { return tab0[2 * np0 + p]; });
+        if ((threadIdx.x & 63) == 0) b_p[slot] = (uint32_t)r;
+    }
     __syncthreads();
     if (!ok) return;
     const TextDesc &d = *dp;

@@ -121,11 +121,17 @@ __global__ __launch_bounds__(256) void k_cgather(wt_levels src, wt_levels dst, c
         return a;
     };
     // the block's words lie between the intervals of its first and last
-    // positions: one full search each, then every thread searches between
+    // positions: one full search each (wave 0 and wave 1), then every thread
+    // searches between
     const uint64_t w0 = (uint64_t)blockIdx.x * blockDim.x;
     const uint64_t p_first = w0 << 6;
     const uint64_t p_last = min(min(w0 + blockDim.x, W) << 6, n) - 1;  // used only when p_first < n
-    if (threadIdx.x < 2 && p_first < n) bnd[threadIdx.x] = search(threadIdx.x ? p_last : p_first, 0, np);
+    if (p_first < n && threadIdx.x < 128) {
+        const uint32_t slot = threadIdx.x >> 6;
+        const uint64_t r = wave_search_last_le(np, slot ? p_last : p_first,
+                                               [&](uint64_t q) { return start((uint32_t)q); });
+        if ((threadIdx.x & 63) == 0) bnd[slot] = (uint32_t)r;
+    }
     __syncthreads();
     const uint64_t w = w0 + threadIdx.x;
     if (w >= W) return;
@@ -320,15 +326,35 @@ __global__ __launch_bounds__(256) void k_mgather(const wt_levels *__restrict__ p
                                                  const uint32_t *tabs, uint64_t stride,
                                                  const uint32_t *mtab, wt_levels dst, uint32_t l)
 {
-    const uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ uint64_t mb[2];
     const uint64_t W = dst.words_per_level;
-    if (w >= W) return;
     const uint64_t np = 1ull << l;
     const uint64_t ne = np * count;
     const uint32_t *ds = mtab + (uint64_t)count * (np - 1);
     const bool wt = (dst.kind == WT_TREE);
+    // start (in the whole) of the (prefix, piece) interval at position m of the
+    // whole's order
+    auto start_at = [&](uint64_t m) -> uint64_t {
+        const uint32_t k = (uint32_t)(m / count), c = (uint32_t)(m % count);
+        const uint32_t p = wt ? k : rev_bits(k, l);
+        return ds[(uint64_t)p * count + c];
+    };
+    // the block's words lie between the intervals of its first and last
+    // positions: one full search each (wave 0 and wave 1)
+    const uint64_t wb0 = (uint64_t)blockIdx.x * blockDim.x;
+    const uint64_t p_first = wb0 << 6;
+    if (p_first < dst.n && threadIdx.x < 128) {
+        const uint64_t p_last = min(min(wb0 + blockDim.x, W) << 6, dst.n) - 1;
+        const uint32_t slot = threadIdx.x >> 6;
+        const uint64_t r = wave_search_last_le(ne, slot ? p_last : p_first, start_at);
+        if ((threadIdx.x & 63) == 0) mb[slot] = r;
+    }
+    __syncthreads();
+    const uint64_t w = wb0 + threadIdx.x;
+    if (w >= W) return;
     const uint64_t b0 = w << 6;
     const uint64_t we = min(b0 + 64, dst.n);
+    const uint64_t mlo = mb[0], mhi = mb[1] + 1;  // set whenever b0 < n
     uint64_t val = 0;
     uint64_t pos = b0;
     uint64_t lo = ne;  // position (in the whole's order) of the previous piece's interval
@@ -347,25 +373,20 @@ __global__ __launch_bounds__(256) void k_mgather(const wt_levels *__restrict__ p
         if (next) {
             lo = lo + 1;
         } else {
-            // start (in the whole) of the interval at position m of its order
-            auto start_at = [&](uint64_t m) -> uint64_t {
-                const uint32_t k = (uint32_t)(m / count), c = (uint32_t)(m % count);
-                const uint32_t p = wt ? k : rev_bits(k, l);
-                return ds[(uint64_t)p * count + c];
-            };
-            uint64_t a = 0, hi = ne;
+            uint64_t a = mlo, hi = mhi;
             if (lo < ne) {
                 // after a piece: a bracket that doubles from its interval
                 // until an interval starts past pos (empty intervals between)
                 uint64_t step = 1;
                 a = lo;
                 hi = lo + 1;
-                while (hi < ne && start_at(hi) <= pos) {
+                while (hi < mhi && start_at(hi) <= pos) {
                     a = hi;
                     step <<= 1;
                     hi = a + step;
                 }
-                if (hi > ne) hi = ne;
+                if (hi > mhi) hi = mhi;
+                if (hi <= a) hi = a + 1;  // never empty
             }
             while (hi - a > 1) {
                 const uint64_t mid = (a + hi) >> 1;

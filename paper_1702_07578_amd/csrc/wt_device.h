@@ -21,6 +21,28 @@ __device__ inline uint32_t find_text(const uint32_t *__restrict__ bases, uint32_
     return lo;
 }
 
+// Largest index p in [0, hi) with key(p) <= pos, for a key that does not
+// decrease and key(0) <= pos, found by one whole wave (every lane active, the
+// same arguments in every lane): each round the 64 lanes probe evenly spaced
+// indexes of the remaining range and a ballot keeps the last probe at or
+// before pos, so 2^15 entries take three rounds of one load each instead of
+// fifteen dependent loads.
+template <typename Key>
+__device__ inline uint64_t wave_search_last_le(uint64_t hi, uint64_t pos, Key key)
+{
+    const uint64_t lane = __lane_id();
+    uint64_t lo = 0;
+    while (hi - lo > 1) {
+        const uint64_t step = (hi - lo + 63) >> 6;
+        const uint64_t p = lo + lane * step;
+        const bool le = p < hi && (uint64_t)key(p < hi ? p : hi - 1) <= pos;
+        const uint64_t m = __ballot(le);  // a prefix of the lanes; lane 0 probes lo
+        lo += (uint64_t)(63 - __clzll((long long)m)) * step;
+        hi = lo + step < hi ? lo + step : hi;
+    }
+    return lo;
+}
+
 // The same among texts [a, b] (bases[a] <= item): for a workgroup whose
 // items are known to lie in the texts of its first and last item.
 __device__ inline uint32_t find_text_in(const uint32_t *__restrict__ bases, uint32_t a, uint32_t b,
