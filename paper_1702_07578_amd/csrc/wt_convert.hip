@@ -471,12 +471,23 @@ __global__ __launch_bounds__(1024) void k_xoffsets(const uint32_t *tab, uint32_t
 __global__ __launch_bounds__(256) void k_xgather(wt_levels wt, const uint32_t *tab, const uint64_t *nodes,
                                                  uint64_t *pool, uint64_t pool_words)
 {
-    const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= pool_words) return;
+    __shared__ uint64_t xb[2];
     const uint64_t ne = (1ull << wt.lg_sigma) - 1;
+    // the nodes of the block's first and last words, by two whole waves (the
+    // grid has no block past the pool)
+    const uint64_t q0 = (uint64_t)blockIdx.x * blockDim.x;
+    if (threadIdx.x < 128) {
+        const uint32_t slot = threadIdx.x >> 6;
+        const uint64_t qe = min(q0 + blockDim.x, pool_words) - 1;
+        const uint64_t r = wave_search_last_le(ne, slot ? qe : q0, [&](uint64_t m) { return nodes[2 * m]; });
+        if ((threadIdx.x & 63) == 0) xb[slot] = r;
+    }
+    __syncthreads();
+    const uint64_t q = q0 + threadIdx.x;
+    if (q >= pool_words) return;
     // last node whose run starts at or before q (empty nodes share the next
-    // node's start, so the last one is not empty)
-    uint64_t lo = 0, hi = ne;
+    // node's start, so the last one is not empty), between the block's nodes
+    uint64_t lo = xb[0], hi = xb[1] + 1;
     while (hi - lo > 1) {
         const uint64_t mid = (lo + hi) >> 1;
         if (nodes[2 * mid] <= q) lo = mid;
