@@ -66,7 +66,13 @@ __device__ inline uint32_t find_text_block(const uint32_t *__restrict__ bases, u
     const uint32_t first = blockIdx.x * blockDim.x;
     const uint32_t last = min(nitems, first + blockDim.x) - 1;
     if (nd == 1) return 0;
-    if (threadIdx.x < 2) ends[threadIdx.x] = find_text(bases, nd, threadIdx.x ? last : first);
+    // the texts of the first and the last item, by waves 0 and 1 (the block
+    // has at least 128 threads, every one of them active here)
+    if (threadIdx.x < 128) {
+        const uint32_t slot = threadIdx.x >> 6;
+        const uint64_t r = wave_search_last_le(nd, slot ? last : first, [&](uint64_t m) { return bases[m]; });
+        if ((threadIdx.x & 63) == 0) ends[slot] = (uint32_t)r;
+    }
     __syncthreads();
     const uint32_t item = first + threadIdx.x;
     if (item >= nitems) return 0;
