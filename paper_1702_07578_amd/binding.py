@@ -68,6 +68,12 @@ class WtPosmap(ctypes.Structure):
                 ("sel1", ctypes.c_void_p), ("X", ctypes.c_void_p)]
 
 
+# PyTorch first: it ships the HIP runtime it was built for, under the same
+# soname as the system's, and whichever is loaded first serves the whole
+# process.  The library must use torch's, the runtime that owns the streams
+# and the memory it is handed.
+import torch  # noqa: E402,F401
+
 lib = ctypes.CDLL(LIB_PATH)
 _v, _u64, _u32, _i, _sz = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int, ctypes.c_size_t
 _LP = ctypes.POINTER(WtLevels)

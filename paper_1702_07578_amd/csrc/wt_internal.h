@@ -12,7 +12,7 @@ namespace wtg {
 
 // Range kernels (histogram, border zeroing) run 512 threads (8 wave64s) per
 // range of consecutive tiles.
-constexpr uint32_t kTileThreads = 512;
+constexpr uint32_t kTileThreads = 256;
 constexpr uint32_t kTileWaves = kTileThreads / 64;
 // The scatter gives every wave a range of its own and walks it one tile at a
 // time; a tile is at most kWaveTile symbols (held in registers, 32 per lane).
