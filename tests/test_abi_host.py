@@ -120,3 +120,20 @@ def test_sorting_build_sizes_and_refusals():
     assert B.wt_ps_build(1, fake, 1000, 1, 8, ctypes.byref(v), fake, need, None) == B.WT_EINVAL  # kind mismatch
     assert B.wt_ps_build(0, ctypes.c_void_p((1 << 20) + 1), 1000, 2, 8, ctypes.byref(v), fake, need,
                          None) == B.WT_EINVAL  # misaligned u16 text
+
+
+def test_binding_uses_torchs_hip_runtime():
+    """Importing the binding first (before torch) must still bind the library
+    to the HIP runtime torch ships: two runtimes in one process would hand the
+    library streams and memory it does not know."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_1702_07578_amd import binding\n"
+            "maps = [l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l]\n"
+            "print('\\n'.join(sorted(set(maps))))\n") % ROOT
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr
+    loaded = [l for l in r.stdout.splitlines() if l.strip()]
+    assert len(loaded) == 1, loaded
+    assert os.sep + "torch" + os.sep in loaded[0], loaded
