@@ -10,8 +10,9 @@
 
 namespace wtg {
 
-// Range kernels (histogram, border zeroing) run 512 threads (8 wave64s) per
-// range of consecutive tiles.
+// The histogram runs 256 threads (4 wave64s) per range of consecutive tiles:
+// with 8 interleaved copies of 256 keys per wave that is 32 KiB of LDS, five
+// workgroups per CU.
 constexpr uint32_t kTileThreads = 256;
 constexpr uint32_t kTileWaves = kTileThreads / 64;
 // The scatter gives every wave a range of its own and walks it one tile at a
@@ -19,8 +20,9 @@ constexpr uint32_t kTileWaves = kTileThreads / 64;
 constexpr uint32_t kWaveTile = 2048;
 // Largest number of levels handled by one pass over the (re-ordered) text.
 constexpr uint32_t kMaxGroupBits = 8;
-// Ranges per text when the text is long enough: four per resident scatter
-// wave (12 per CU on 256 CUs), so that the last round of ranges is short.
+// Ranges per text when the text is long enough: three rounds of the 4096
+// scatter waves resident at four per SIMD on 256 CUs (the five-wave pair
+// kernel measured no faster with other counts).
 constexpr uint32_t kTargetRanges = 12288;
 // Ranges per chunk of the column scans over the range histograms.
 constexpr uint32_t kBorderChunk = 32;
