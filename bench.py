@@ -288,17 +288,17 @@ def run_serve(args):
     s_big = items[big][5]
     qpos = torch.from_numpy(inputs.u64(qm, items[big][1], 5, 0).view(np.int64)).to(dev)
     qsym = s_big.access(qpos)
-    ones = torch.ones(qm, dtype=torch.int64, device=dev)
+    qk = s_big.rank(qsym, qpos) + 1  # select(T[j], rank + 1) = j
     torch.cuda.synchronize()
     q0, q1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     q0.record()
     s_big.access(qpos)
     s_big.rank(qsym, qpos)
-    s_big.select(qsym, ones)
+    s_big.select(qsym, qk)
     q1.record()
     torch.cuda.synchronize()
     q_batch_s = q0.elapsed_time(q1) / 3 / 1e3
-    del batch, items, s_big, qpos, qsym, ones
+    del batch, items, s_big, qpos, qsym, qk
     torch.cuda.empty_cache()
     log(f"batched build capacity {capacity:.3e} symbols/s; one 2^20 query batch {q_batch_s * 1e3:.3f} ms")
 
@@ -568,19 +568,31 @@ def main():
             raise SystemExit(f"access check failed for kind {k}")
 
     # query throughput (extra): 2^20 access / rank / select on each structure
+    # at random positions j: access(j), rank(c, j) and select(c, k) with
+    # c = T[j] and k = rank(c, j) + 1 (so the select answers j)
     m = 1 << 20
-    qpos = torch.from_numpy(inputs.u64(m, n, 98, 1).view(np.int64)).to(dev)
-    qsym = torch.from_numpy(text[inputs.u64(m, n, 97, 2).astype(np.int64)].astype(np.uint32).view(np.int32)).to(dev)
-    qk = torch.ones(m, dtype=torch.int64, device=dev)
+    qpos_h = inputs.u64(m, n, 98, 1)
+    qpos = torch.from_numpy(qpos_h.view(np.int64)).to(dev)
+    qsym = torch.from_numpy(text[qpos_h.astype(np.int64)].astype(np.uint32).view(np.int32)).to(dev)
+    qk = {k: s.rank(qsym, qpos) + 1 for k, s in structs.items()}
+    torch.cuda.synchronize()
     qe0, qe1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     qe0.record(stream)
-    for s in structs.values():
-        s.access(qpos)
-        s.rank(qsym, qpos)
-        s.select(qsym, qk)
+    qres = {}
+    for k, s in structs.items():
+        qres[k] = (s.access(qpos), s.rank(qsym, qpos), s.select(qsym, qk[k]))
     qe1.record(stream)
     torch.cuda.synchronize()
     q_per_s = 6 * m / (qe0.elapsed_time(qe1) / 1e3)
+    # self-check of the timed answers (Section 2 definitions): access
+    # reconstructs T, select(c, rank(c, j) + 1) = j, rank(c, select(c, k)) = k - 1
+    for k, s in structs.items():
+        acc, rk, sel = qres[k]
+        if not torch.equal(acc, qsym) or not torch.equal(rk + 1, qk[k]) or not torch.equal(sel, qpos):
+            raise SystemExit(f"query self-check failed for kind {k}")
+        if not torch.equal(s.rank(qsym, sel), qk[k] - 1):
+            raise SystemExit(f"rank(select) self-check failed for kind {k}")
+    del qres, qk
 
     # conversion between the two structures (Section 5.1) and the Lemma 5
     # position map, on the measured outputs: each converted structure must

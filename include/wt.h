@@ -233,6 +233,14 @@ int wt_merge(const wt_levels *parts, uint32_t count, wt_levels *dst, void *d_ws,
 size_t wt_pair_workspace_bytes(uint64_t n, uint32_t sym_bytes, uint32_t lg_sigma);
 int wt_pair_build(const void *d_text, uint64_t n, uint32_t sym_bytes, uint32_t lg_sigma, wt_levels *wt,
                   wt_levels *wm, void *d_ws, size_t ws_bytes, hipStream_t stream);
+/* Same, with tuning knobs (tune may be NULL: then identical to the calls
+ * above).  tune->grid sets the ranges of consecutive tiles per text, so a
+ * short text can be cut into ranges of several tiles each; tune->group_bits
+ * below lg_sigma takes the several-group path (WM build, then the WT gathered
+ * from it); tune->persist caps the workgroups of every launch. */
+size_t wt_pair_workspace_bytes_tuned(uint64_t n, uint32_t sym_bytes, uint32_t lg_sigma, const wt_tune *tune);
+int wt_pair_build_tuned(const void *d_text, uint64_t n, uint32_t sym_bytes, uint32_t lg_sigma, wt_levels *wt,
+                        wt_levels *wm, void *d_ws, size_t ws_bytes, const wt_tune *tune, hipStream_t stream);
 
 /*
  * Construction by sorting (Section 3.2, construction using sorting,

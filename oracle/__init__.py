@@ -21,6 +21,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "wt_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+_PAR_SRC = os.path.join(_HERE, "wt_oracle_par.c")
+_PAR_LIB = os.path.join(_HERE, "liboracle_par.so")
 
 WT, WM = 0, 1
 Q_ACCESS, Q_RANK, Q_SELECT = 0, 1, 2
@@ -37,6 +39,15 @@ class OracleError(RuntimeError):
 def compile_library(src: str = _SRC, out: str = _LIB, extra_flags=()) -> str:
     """Compile the oracle with gcc into a shared library (always recompiles)."""
     cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC",
+           *extra_flags, "-o", out + ".tmp", src]
+    subprocess.run(cmd, check=True, cwd=os.path.dirname(src))
+    os.replace(out + ".tmp", out)
+    return out
+
+
+def compile_par_library(src: str = _PAR_SRC, out: str = _PAR_LIB, extra_flags=()) -> str:
+    """Compile the all-cores form of the top-down builder (OpenMP)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fopenmp", "-shared", "-fPIC",
            *extra_flags, "-o", out + ".tmp", src]
     subprocess.run(cmd, check=True, cwd=os.path.dirname(src))
     os.replace(out + ".tmp", out)
@@ -65,6 +76,7 @@ def _bind(lib):
         "orc_select_bv": (_u64, [_u64p, _u64, _u64, _u32]),
         "orc_directory": (_int, [_u64p, _u64, _u64, _u32p, _u32p, _u32p]),
         "orc_queries_def": (_int, [_vp, _u64, _u32, _u32, _int, _u32p, _u64p, _u64, _u64p]),
+        "orc_rank_scan": (_int, [_vp, _u64, _u32, _u32, _u32p, _u64p, _u64, _u64p]),
         "orc_queries_walk": (_int, [_int, _u64p, _u64, _u64p, _u64, _u32, _int, _u32p, _u64p,
                                     _u64, _u64p]),
         "orc_sample_level": (_int, [_int, _vp, _u64, _u32, _u32, _u32, _u64p, _u64, _u8p]),
@@ -83,8 +95,43 @@ class Oracle:
     compiled from another source file, e.g. a deliberately broken copy used to
     show that the pins catch mistakes)."""
 
-    def __init__(self, lib_path: str):
+    def __init__(self, lib_path: str, par_path: str | None = None):
         self.lib = _bind(ctypes.CDLL(lib_path))
+        self._par_path = par_path
+        self._par = None
+
+    def _par_lib(self):
+        if self._par is None:
+            path = self._par_path
+            if path is None:
+                if not os.path.exists(_PAR_LIB) or os.path.getmtime(_PAR_LIB) < os.path.getmtime(_PAR_SRC):
+                    compile_par_library()
+                path = _PAR_LIB
+            lib = ctypes.CDLL(path)
+            lib.orc_par_build.restype = _int
+            lib.orc_par_build.argtypes = [_int, _vp, _u64, _u32, _u32, _u64p, _u64, _u64p, _int]
+            lib.orc_par_max_threads.restype = _int
+            lib.orc_par_max_threads.argtypes = []
+            self._par = lib
+        return self._par
+
+    def par_threads(self) -> int:
+        """Threads the all-cores builder uses by default (OpenMP's count)."""
+        return int(self._par_lib().orc_par_max_threads())
+
+    def par_build(self, kind: int, text, L: int, threads: int = 0):
+        """The same levels and zero counts as build(), computed by the
+        top-down algorithm on `threads` host threads (0: all OpenMP offers)."""
+        t, b = self._text(text)
+        n = t.size
+        W = self.words_per_level(n)
+        bits = np.zeros((max(L, 1), max(W, 1)), dtype=np.uint64)
+        zeros = np.zeros(max(L, 1), dtype=np.uint64)
+        rc = self._par_lib().orc_par_build(kind, t.ctypes.data, n, b, L, self._p(bits, _u64p), max(W, 1),
+                                           self._p(zeros, _u64p), threads)
+        if rc != OK:
+            raise OracleError(rc, "par_build")
+        return bits[:L, :W], zeros[:L].copy()
 
     # -- helpers -----------------------------------------------------------
     @staticmethod
@@ -173,6 +220,19 @@ class Oracle:
         if rc != OK:
             raise OracleError(rc, "queries_def")
         return out[: a.size]
+
+    def rank_scan(self, text, L: int, syms, positions):
+        """rank_c(i) for pairs (syms[q], positions[q]) by one scan of the
+        text (no occurrence lists; for long texts, L <= 26)."""
+        t, b = self._text(text)
+        p = np.ascontiguousarray(positions, dtype=np.uint64)
+        s = np.ascontiguousarray(syms, dtype=np.uint32)
+        out = np.zeros(max(p.size, 1), dtype=np.uint64)
+        rc = self.lib.orc_rank_scan(t.ctypes.data, t.size, b, L, self._p(s, _u32p), self._p(p, _u64p), p.size,
+                                    self._p(out, _u64p))
+        if rc != OK:
+            raise OracleError(rc, "rank_scan")
+        return out[: p.size]
 
     def queries_walk(self, kind: int, bits, zeros, n: int, L: int, op: int, syms, args):
         bb = np.ascontiguousarray(bits, dtype=np.uint64)

@@ -342,6 +342,57 @@ int orc_queries_def(const void *text, uint64_t n, uint32_t sym_bytes, uint32_t L
     return ORC_OK;
 }
 
+/* rank_c(i) = #{ j < i : T[j] = c } (Section 2) for many (c, i) pairs on a
+ * long text, without the occurrence lists: the queries are visited in
+ * increasing i while one left-to-right scan of the text keeps, for every
+ * symbol, how often it has occurred so far.  The same sentinels as above
+ * (UINT64_MAX for i > n, 0 for c >= 2^L).  Needs 2^L counters: L <= 26. */
+typedef struct {
+    uint64_t pos;
+    uint64_t q;
+} rq_t;
+
+static int rq_cmp(const void *x, const void *y)
+{
+    const rq_t *a = (const rq_t *)x, *b = (const rq_t *)y;
+    if (a->pos != b->pos) return a->pos < b->pos ? -1 : 1;
+    return a->q < b->q ? -1 : (a->q > b->q);
+}
+
+int orc_rank_scan(const void *text, uint64_t n, uint32_t sym_bytes, uint32_t L, const uint32_t *syms,
+                  const uint64_t *pos, uint64_t m, uint64_t *out)
+{
+    if (L > 26) return ORC_EINVAL;
+    int rc = orc_check_symbols(text, n, sym_bytes, L);
+    if (rc != ORC_OK) return rc;
+    uint64_t sigma_end = (uint64_t)1 << L;
+    uint64_t *count = (uint64_t *)calloc((size_t)sigma_end, sizeof(uint64_t));
+    rq_t *order = (rq_t *)malloc((size_t)(m ? m : 1) * sizeof(rq_t));
+    if (!count || !order) {
+        free(count);
+        free(order);
+        return ORC_ENOMEM;
+    }
+    for (uint64_t q = 0; q < m; q++) {
+        order[q].pos = pos[q];
+        order[q].q = q;
+    }
+    qsort(order, (size_t)m, sizeof(rq_t), rq_cmp);
+    uint64_t i = 0; /* count[] covers T[0, i) */
+    for (uint64_t r = 0; r < m; r++) {
+        uint64_t p = order[r].pos, q = order[r].q;
+        if (p > n) {
+            out[q] = UINT64_MAX;
+            continue;
+        }
+        while (i < p) count[sym_at(text, sym_bytes, i++)]++;
+        out[q] = (syms[q] < sigma_end) ? count[syms[q]] : 0;
+    }
+    free(count);
+    free(order);
+    return ORC_OK;
+}
+
 /* ---- queries by walking the oracle's own levels (textbook walks) -------- */
 
 int orc_queries_walk(int kind, const uint64_t *bits, uint64_t W, const uint64_t *zeros,

@@ -46,6 +46,9 @@ int orc_directory(const uint64_t *words, uint64_t n, uint64_t W, uint32_t *rank_
 /* queries: op 0 access(args=i), 1 rank(syms=c, args=i), 2 select(syms=c, args=k) */
 int orc_queries_def(const void *text, uint64_t n, uint32_t sym_bytes, uint32_t L, int op,
                     const uint32_t *syms, const uint64_t *args, uint64_t m, uint64_t *out);
+/* rank only, for long texts: one scan of the text, queries in position order (L <= 26) */
+int orc_rank_scan(const void *text, uint64_t n, uint32_t sym_bytes, uint32_t L, const uint32_t *syms,
+                  const uint64_t *pos, uint64_t m, uint64_t *out);
 int orc_queries_walk(int kind, const uint64_t *bits, uint64_t W, const uint64_t *zeros,
                      uint64_t n, uint32_t L, int op, const uint32_t *syms, const uint64_t *args,
                      uint64_t m, uint64_t *out);

@@ -104,6 +104,8 @@ _SIGS = {
     "wt_merge": (_i, [_LP, _u32, _LP, _v, _sz, _v]),
     "wt_pair_workspace_bytes": (_sz, [_u64, _u32, _u32]),
     "wt_pair_build": (_i, [_v, _u64, _u32, _u32, _LP, _LP, _v, _sz, _v]),
+    "wt_pair_workspace_bytes_tuned": (_sz, [_u64, _u32, _u32, _TP]),
+    "wt_pair_build_tuned": (_i, [_v, _u64, _u32, _u32, _LP, _LP, _v, _sz, _TP, _v]),
     "wt_pair_build_recorded": (_i, [_v, _u64, _u32, _u32, _LP, _LP, _v, _sz, _v, ctypes.POINTER(_v),
                                     ctypes.POINTER(_u32), _u32, ctypes.POINTER(_u32)]),
     "wt_ps_workspace_bytes": (_sz, [_u64, _u32, _u32]),
@@ -271,22 +273,29 @@ def build(d_text, n: int, sym_bytes: int, L: int, kind: int, tune=None, stream=N
     return s
 
 
-def pair_build(d_text, n: int, sym_bytes: int, L: int, stream=None, ws=None, out=None):
-    """The WT and the WM of one text (wt_pair_build): one pass writes both when
-    L <= 8.  Returns (wt, wm) Structures; out = (wt, wm) reuses buffers."""
+def pair_build(d_text, n: int, sym_bytes: int, L: int, stream=None, ws=None, out=None, tune=None):
+    """The WT and the WM of one text (wt_pair_build, or wt_pair_build_tuned
+    with tune): one pass writes both when L <= 8.  Returns (wt, wm)
+    Structures; out = (wt, wm) reuses buffers."""
     torch = _torch()
     dev = d_text.device
     wt, wm = out if out is not None else (Structure(n, L, WT_TREE, device=dev), Structure(n, L, WT_MATRIX, device=dev))
-    need = int(wt_pair_workspace_bytes(n, sym_bytes, L))
+    need = int(wt_pair_workspace_bytes_tuned(n, sym_bytes, L, _tune_ptr(tune)))
     if need == 0:
-        check(wt_pair_build(ctypes.c_void_p(d_text.data_ptr() if n else 0), n, sym_bytes, L, ctypes.byref(wt.view),
-                            ctypes.byref(wm.view), None, 0, None), "wt_pair_build")
+        check(wt_pair_build_tuned(ctypes.c_void_p(d_text.data_ptr() if n else 0), n, sym_bytes, L,
+                                  ctypes.byref(wt.view), ctypes.byref(wm.view), None, 0, _tune_ptr(tune), None),
+              "wt_pair_build")
         raise WtError(WT_EINVAL, "wt_pair_workspace_bytes")
     if ws is None or ws.numel() < need:
         ws = torch.empty(need, dtype=torch.uint8, device=dev)
     ptr = ctypes.c_void_p(d_text.data_ptr()) if n > 0 else ctypes.c_void_p(ws.data_ptr())
-    check(wt_pair_build(ptr, n, sym_bytes, L, ctypes.byref(wt.view), ctypes.byref(wm.view),
-                        ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(stream)), "wt_pair_build")
+    if tune is None:
+        rc = wt_pair_build(ptr, n, sym_bytes, L, ctypes.byref(wt.view), ctypes.byref(wm.view),
+                           ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(stream))
+    else:
+        rc = wt_pair_build_tuned(ptr, n, sym_bytes, L, ctypes.byref(wt.view), ctypes.byref(wm.view),
+                                 ctypes.c_void_p(ws.data_ptr()), ws.numel(), _tune_ptr(tune), _stream_handle(stream))
+    check(rc, "wt_pair_build")
     wt._ws = ws
     return wt, wm
 

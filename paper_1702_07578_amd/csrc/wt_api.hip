@@ -334,10 +334,10 @@ namespace wtg {
 // groups, the WM is built and the WT gathered from its intervals (the
 // conversion), which costs less than a second multi-group build.
 static int pair_one(const void *d_text, uint64_t n, uint32_t b, uint32_t L, wt_levels *wt,
-                    wt_levels *wm, void *d_ws, size_t ws_bytes, const LaunchCtx &ctx)
+                    wt_levels *wm, void *d_ws, size_t ws_bytes, const wt_tune *tune, const LaunchCtx &ctx)
 {
     WsPlan p;
-    int rc = plan_text(n, b, L, WT_TREE, nullptr, p);
+    int rc = plan_text(n, b, L, WT_TREE, tune, p);
     if (rc != WT_OK) return rc;
     if ((rc = check_out(wt, n, L, WT_TREE)) != WT_OK) return rc;
     if ((rc = check_out(wm, n, L, WT_MATRIX)) != WT_OK) return rc;
@@ -345,11 +345,11 @@ static int pair_one(const void *d_text, uint64_t n, uint32_t b, uint32_t L, wt_l
     if ((uintptr_t)d_text % b) return WT_EINVAL;
     if (!d_ws) return WT_EINVAL;
     if (L == 0) {
-        if ((rc = build_one(WT_TREE, d_text, n, b, L, wt, d_ws, ws_bytes, nullptr, ctx)) != WT_OK) return rc;
-        return build_one(WT_MATRIX, d_text, n, b, L, wm, d_ws, ws_bytes, nullptr, ctx);
+        if ((rc = build_one(WT_TREE, d_text, n, b, L, wt, d_ws, ws_bytes, tune, ctx)) != WT_OK) return rc;
+        return build_one(WT_MATRIX, d_text, n, b, L, wm, d_ws, ws_bytes, tune, ctx);
     }
     if (p.d.G != 1) {
-        if ((rc = build_one(WT_MATRIX, d_text, n, b, L, wm, d_ws, ws_bytes, nullptr, ctx)) != WT_OK) return rc;
+        if ((rc = build_one(WT_MATRIX, d_text, n, b, L, wm, d_ws, ws_bytes, tune, ctx)) != WT_OK) return rc;
         // the build's workspace is free again once the stream passes it
         return ::convert_one(wm, wt, d_ws, ws_bytes, ctx);
     }
@@ -374,19 +374,20 @@ static int pair_one(const void *d_text, uint64_t n, uint32_t b, uint32_t L, wt_l
     if (launch_init(p.d, d_desc, ctx) != hipSuccess) return WT_EHIP;
     DevBases bb;
     bb.walk.assign(s.walk_items.size(), nullptr);
-    if (run_build(d_desc, s, bb, 0, ctx) != hipSuccess) return WT_EHIP;
-    if (launch_dirs(d_desc2, nullptr, 1, s.dir_items, s.max_levels, false, 0, ctx) != hipSuccess)
+    const uint32_t cap = tune ? tune->persist : 0;
+    if (run_build(d_desc, s, bb, cap, ctx) != hipSuccess) return WT_EHIP;
+    if (launch_dirs(d_desc2, nullptr, 1, s.dir_items, s.max_levels, false, cap, ctx) != hipSuccess)
         return WT_EHIP;
     return WT_OK;
 }
 
-static size_t pair_ws_bytes(uint64_t n, uint32_t b, uint32_t L)
+static size_t pair_ws_bytes(uint64_t n, uint32_t b, uint32_t L, const wt_tune *tune)
 {
     WsPlan p;
-    if (plan_text(n, b, L, WT_TREE, nullptr, p) != WT_OK) return 0;
+    if (plan_text(n, b, L, WT_TREE, tune, p) != WT_OK) return 0;
     if (p.d.G == 1 && L > 0) return p.bytes + 2 * align_up(sizeof(TextDesc), 256) + 256;
     WsPlan q;
-    if (plan_text(n, b, L, WT_MATRIX, nullptr, q) != WT_OK) return 0;
+    if (plan_text(n, b, L, WT_MATRIX, tune, q) != WT_OK) return 0;
     size_t need = q.bytes + align_up(sizeof(TextDesc), 256) + 256;
     if (L > 0) {
         const size_t conv = wt_convert_workspace_bytes(n, L);
@@ -457,14 +458,26 @@ int wt_build_tuned(wt_kind kind, const void *d_text, uint64_t n, uint32_t sym_by
 
 size_t wt_pair_workspace_bytes(uint64_t n, uint32_t sym_bytes, uint32_t lg_sigma)
 {
-    return pair_ws_bytes(n, sym_bytes, lg_sigma);
+    return pair_ws_bytes(n, sym_bytes, lg_sigma, nullptr);
+}
+
+size_t wt_pair_workspace_bytes_tuned(uint64_t n, uint32_t sym_bytes, uint32_t lg_sigma, const wt_tune *tune)
+{
+    return pair_ws_bytes(n, sym_bytes, lg_sigma, tune);
 }
 
 int wt_pair_build(const void *d_text, uint64_t n, uint32_t sym_bytes, uint32_t lg_sigma, wt_levels *wt,
                   wt_levels *wm, void *d_ws, size_t ws_bytes, hipStream_t stream)
 {
     LaunchCtx ctx{stream, nullptr, nullptr};
-    return pair_one(d_text, n, sym_bytes, lg_sigma, wt, wm, d_ws, ws_bytes, ctx);
+    return pair_one(d_text, n, sym_bytes, lg_sigma, wt, wm, d_ws, ws_bytes, nullptr, ctx);
+}
+
+int wt_pair_build_tuned(const void *d_text, uint64_t n, uint32_t sym_bytes, uint32_t lg_sigma, wt_levels *wt,
+                        wt_levels *wm, void *d_ws, size_t ws_bytes, const wt_tune *tune, hipStream_t stream)
+{
+    LaunchCtx ctx{stream, nullptr, nullptr};
+    return pair_one(d_text, n, sym_bytes, lg_sigma, wt, wm, d_ws, ws_bytes, tune, ctx);
 }
 
 int wt_build(const void *d_text, uint64_t n, uint32_t sym_bytes, uint32_t lg_sigma,
@@ -1229,7 +1242,7 @@ extern "C" int wt_pair_build_recorded(const void *d_text, uint64_t n, uint32_t s
     if ((capacity && (!events || !kernel_ids)) || !recorded) return WT_EINVAL;
     RecState r{stream, events, kernel_ids, capacity, 0, false};
     LaunchCtx ctx{stream, rec_after, &r};
-    int rc = pair_one(d_text, n, sym_bytes, lg_sigma, wt, wm, d_ws, ws_bytes, ctx);
+    int rc = pair_one(d_text, n, sym_bytes, lg_sigma, wt, wm, d_ws, ws_bytes, nullptr, ctx);
     *recorded = r.count;
     if (rc == WT_OK && r.failed) rc = WT_EHIP;
     return rc;

@@ -294,6 +294,56 @@ def check_queries(o):
                                                  [c for c, _ in ks], [k for _, k in ks]), sc)
 
 
+def check_rank_scan(o):
+    """The one-scan rank (for long texts) against counting over the text
+    (Section 2: rank_c(i) = occurrences of c in T[0, i)), with the queries
+    in no particular order, repeated positions, symbols that never occur,
+    c >= 2^L and i > n."""
+    rng = np.random.default_rng(23)
+    for _ in range(40):
+        L = int(rng.integers(0, 9))
+        n = int(rng.integers(0, 300))
+        dt = np.uint8 if L <= 8 else np.uint16
+        T = rng.integers(0, 1 << L, size=n, dtype=np.uint64).astype(dt)
+        Tl = [int(x) for x in T]
+        m = int(rng.integers(1, 60))
+        cs = [int(c) for c in rng.integers(0, (1 << L) + 2, size=m)]
+        ps = [int(p) for p in rng.integers(0, n + 3, size=m)]
+        got = o.rank_scan(T, L, cs, ps)
+        for c, p, r in zip(cs, ps, got):
+            want = 2**64 - 1 if p > n else (0 if c >= (1 << L) else Tl[:p].count(c))
+            assert int(r) == want, ("rank_scan", L, n, c, p, int(r), want)
+
+
+def check_par_build(o):
+    """The all-cores builder equals the single-threaded one (itself pinned by
+    the checks above) for many thread counts, including more threads than
+    64-symbol slices, empty texts, one level and no levels; it refuses an
+    out-of-range symbol."""
+    import oracle
+    rng = np.random.default_rng(29)
+    cases = [(0, 3), (1, 1), (63, 2), (64, 7), (65, 8), (700, 5), (5000, 12), (3000, 16), (2000, 20)]
+    for _ in range(12):
+        cases.append((int(rng.integers(0, 3000)), int(rng.integers(0, 11))))
+    for n, L in cases:
+        dt = np.uint8 if L <= 8 else (np.uint16 if L <= 16 else np.uint32)
+        T = rng.integers(0, 1 << L, size=n, dtype=np.uint64).astype(dt)
+        if n > 10 and L > 1:
+            T[: n // 3] = T[0]  # a long run of one symbol (one node holds many slices)
+        for kind in (WT, WM):
+            want_b, want_z = o.build(kind, T, L)
+            for threads in (1, 2, 3, 7, 16):
+                b, z = o.par_build(kind, T, L, threads)
+                assert np.array_equal(b, want_b), ("par_build levels", kind, n, L, threads)
+                assert np.array_equal(z, want_z), ("par_build zeros", kind, n, L, threads)
+    try:
+        o.par_build(WM, np.array([0, 9, 1], dtype=np.uint8), 3, 2)
+    except oracle.OracleError as e:
+        assert e.code == oracle.ERANGE
+    else:
+        raise AssertionError("symbol 9 with 3 levels must be rejected")
+
+
 def check_rank_select_bv(o):
     rng = np.random.default_rng(13)
     for n in (0, 1, 63, 64, 65, 200, 700):
@@ -427,5 +477,5 @@ def check_errors(o):
 
 
 ALL_CHECKS = [check_golden, check_printed_small_facts, check_levels_brute, check_wide_symbols,
-              check_invariants, check_queries, check_rank_select_bv, check_directory,
+              check_invariants, check_queries, check_rank_scan, check_par_build, check_rank_select_bv, check_directory,
               check_sample_level, check_map_wt_to_wm, check_pointer_tree, check_errors]

@@ -62,6 +62,44 @@ def _check_access(T, s, rng):
     assert np.array_equal(got, T[p.astype(np.int64)].astype(np.uint32)), "access"
 
 
+def _check_rank_select(orc, T, L, s, rng):
+    """rank at sampled (T[j], j) and at sampled (random symbol, position)
+    pairs equals the oracle's count; select inverts rank both ways."""
+    import torch
+    n = T.size
+    j = rng.integers(0, n, size=SAMPLES, dtype=np.uint64)
+    c = T[j.astype(np.int64)].astype(np.uint32)
+    # also symbols that are not the one at the position, and position n
+    c2 = rng.integers(0, 1 << L, size=SAMPLES, dtype=np.uint64).astype(np.uint32)
+    j2 = rng.integers(0, n + 1, size=SAMPLES, dtype=np.uint64)
+    j2[0] = n
+    syms = np.concatenate([c, c2])
+    pos = np.concatenate([j, j2])
+    dev = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a).view(dt)).cuda()
+    got = s.rank(dev(syms, np.int32), dev(pos, np.int64)).cpu().numpy().view(np.uint64)
+    want = orc.rank_scan(T, L, syms, pos)
+    bad = np.flatnonzero(got != want)
+    assert bad.size == 0, f"rank differs at {bad.size} of {syms.size} samples, first {bad[0]}"
+    # select_c(rank_c(j) + 1) = j for c = T[j]
+    k = got[:SAMPLES] + 1
+    sel = s.select(dev(c, np.int32), dev(k, np.int64)).cpu().numpy().view(np.uint64)
+    assert np.array_equal(sel, j), "select(c, rank(c, j) + 1) != j"
+    # rank_c(select_c(k)) = k - 1 and T[select_c(k)] = c, for k up to rank_c(n)
+    tot = s.rank(dev(c2, np.int32), dev(np.full(SAMPLES, n, dtype=np.uint64), np.int64)).cpu().numpy().view(np.uint64)
+    have = tot > 0
+    k2 = (rng.integers(0, 1 << 62, size=SAMPLES, dtype=np.uint64) % np.maximum(tot, 1)) + 1
+    c3, k3 = c2[have], k2[have]
+    if c3.size:
+        p3 = s.select(dev(c3, np.int32), dev(k3, np.int64)).cpu().numpy().view(np.uint64)
+        assert (p3 < n).all(), "select of an existing occurrence out of range"
+        assert np.array_equal(T[p3.astype(np.int64)].astype(np.uint32), c3), "T[select(c, k)] != c"
+        r3 = s.rank(dev(c3, np.int32), dev(p3, np.int64)).cpu().numpy().view(np.uint64)
+        assert np.array_equal(r3, k3 - 1), "rank(c, select(c, k)) != k - 1"
+    # past the last occurrence: the sentinel
+    over = s.select(dev(c2, np.int32), dev(tot + 1, np.int64)).cpu().numpy().view(np.uint64)
+    assert (over == np.uint64(2**64 - 1)).all(), "select past the last occurrence"
+
+
 @pytest.mark.parametrize("workload", ["uniform256", "markov96", "markov4", "zipf20", "uniform16"])
 def test_workload_full_size(orc, workload):
     import torch
@@ -77,6 +115,7 @@ def test_workload_full_size(orc, workload):
         torch.cuda.synchronize()
         _check_structure(orc, T, L, kind, s, rng)
         _check_access(T, s, rng)
+        _check_rank_select(orc, T, L, s, rng)
         built[kind] = s
     # the pair build (the benchmark's step) writes exactly what the checked
     # separate builds wrote: level words, Z and the defined directory entries

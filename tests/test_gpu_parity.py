@@ -38,14 +38,16 @@ def test_small_edges(orc, n, L):
         assert_matches_oracle(orc, T, L, kind, gpu_build(T, L, kind))
 
 
-@pytest.mark.parametrize("tile_log2", [10, 12])
-@pytest.mark.parametrize("L", [2, 5, 8])
-def test_many_tiles_ragged_tail(orc, tile_log2, L):
+@pytest.mark.parametrize("grid", [2, 3])
+@pytest.mark.parametrize("L", [2, 5, 7, 8])
+def test_many_tiles_ragged_tail(orc, grid, L):
+    """Ranges of several 2048-symbol tiles (tune.grid ranges per text) and a
+    short last tile."""
     B = lib()
-    n = 7 * (1 << tile_log2) + 37
+    n = 7 * 2048 + 37  # 8 tiles in grid ranges of 3 or 4 tiles
     T = _rand(n, L, seed=7 + L)
     for kind in (WT, WM):
-        s = gpu_build(T, L, kind, tune=B.make_tune(tile_log2=tile_log2))
+        s = gpu_build(T, L, kind, tune=B.make_tune(grid=grid))
         assert_matches_oracle(orc, T, L, kind, s)
 
 

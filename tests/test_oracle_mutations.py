@@ -61,6 +61,12 @@ MUTATIONS = {
                              "uint64_t e = ((uint64_t)1 << l) - 1 + orc_reverse_bits(prefix_of(L, l, a), l);"),
     # pointer tree: bits of a node in reverse text order
     "ptree_reverse_text": ("uint64_t q = fill[e]++;", "uint64_t q = nodes[2 * e + 1] - 1 - fill[e]++;"),
+    # one-scan rank counts T[0, i] instead of T[0, i)
+    "rank_scan_inclusive": ("while (i < p) count[sym_at(text, sym_bytes, i++)]++;",
+                            "while (i <= p && i < n) count[sym_at(text, sym_bytes, i++)]++;"),
+    # one-scan rank answers in the sorted order instead of the caller's
+    "rank_scan_sorted_order": ("out[q] = (syms[q] < sigma_end) ? count[syms[q]] : 0;",
+                               "out[r] = (syms[r] < sigma_end) ? count[syms[r]] : 0;"),
     # WM select walk forgets the Z offset
     "walk_wm_select_z": ("p = b ? orc_select_bv(lv, n, p - zeros[l] + 1, 1)", "p = b ? orc_select_bv(lv, n, p + 1, 1)"),
 }
@@ -100,3 +106,42 @@ def test_planted_mistake_is_caught(tmp_path, name):
     failed = json.loads(lines[-1]) if lines else []
     # a pin that fails, or a mutant that crashes before any pin finishes, is caught
     assert failed or r.returncode != 0, f"no pin caught the planted mistake {name}"
+
+
+# planted mistakes in the all-cores builder (wt_oracle_par.c)
+PAR_MUTATIONS = {
+    # threads' destinations handed out in reverse thread order (unstable)
+    "par_threads_reversed": ("for (int t = 0; t < T; t++) {\n                uint64_t *c = cnt + ((uint64_t)t * nodes + k) * 2;",
+                             "for (int t = T - 1; t >= 0; t--) {\n                uint64_t *c = cnt + ((uint64_t)t * nodes + k) * 2;"),
+    # the ones of a node start right after the node's start (zeros overwritten)
+    "par_ones_at_node_start": ("uint64_t zc = run, oc = run + z;", "uint64_t zc = run, oc = run;"),
+    # the WT split ignores the nodes (a WM-like global split)
+    "par_wt_no_nodes": ("const uint64_t node = (kind == ORC_WT && l > 0) ? (a >> (L - l)) : 0;\n                tmp",
+                        "const uint64_t node = 0;\n                tmp"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(PAR_MUTATIONS))
+def test_planted_mistake_in_par_builder_is_caught(tmp_path, name):
+    old, new = PAR_MUTATIONS[name]
+    src_dir = os.path.dirname(oracle.__file__)
+    src = open(os.path.join(src_dir, "wt_oracle_par.c")).read()
+    assert src.count(old) == 1, f"mutation anchor for {name} not found exactly once"
+    shutil.copy(os.path.join(src_dir, "wt_oracle.h"), tmp_path / "wt_oracle.h")
+    (tmp_path / "wt_oracle_par.c").write_text(src.replace(old, new))
+    par = oracle.compile_par_library(str(tmp_path / "wt_oracle_par.c"), str(tmp_path / "libmutpar.so"))
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = (
+        "import sys\n"
+        f"sys.path.insert(0, {root!r})\n"
+        "import oracle\n"
+        "from tests import pins\n"
+        f"m = oracle.Oracle(oracle._LIB, par_path={par!r})\n"
+        "try:\n"
+        "    pins.check_par_build(m)\n"
+        "except Exception:\n"
+        "    print('CAUGHT', flush=True)\n"
+    )
+    oracle.load()  # the single-threaded oracle, compiled if needed
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert "CAUGHT" in r.stdout or r.returncode != 0, f"no pin caught the planted mistake {name}"
