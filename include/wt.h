@@ -243,6 +243,31 @@ int wt_pair_build_tuned(const void *d_text, uint64_t n, uint32_t sym_bytes, uint
                         wt_levels *wm, void *d_ws, size_t ws_bytes, const wt_tune *tune, hipStream_t stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * wt_pair_build with its workspace taken from a scratch array that the
+ * library keeps on every GPU it runs on (WT_NOALLOC_SCRATCH_BYTES, held from
+ * the library's code object load until the process ends; its device address
+ * is looked up once per device, on the first call made with that device
+ * current).  The caller still passes the text and the two bound output views;
+ * outputs, status and argument errors are those of wt_pair_build.  Allocates
+ * nothing and copies nothing from the host: every step is a kernel launch on
+ * `stream`.
+ * WT_ENOSPACE, before any device work, when the text needs more workspace than
+ * the scratch holds (wt_pair_workspace_bytes(n, sym_bytes, lg_sigma) >
+ * WT_NOALLOC_SCRATCH_BYTES; for example byte texts of 2^30 symbols with up to
+ * 8 levels fit, 2^26 symbols of 16 levels do not).  WT_EHIP if the scratch's
+ * device address cannot be obtained.
+ * All calls on one GPU share that GPU's scratch, which keeps the last call's
+ * contents (no kernel reads a workspace entry it has not written in the same
+ * call): calls that overlap on one GPU, from any stream or thread, race and
+ * must be serialised by the caller.
+ */
+#define WT_NOALLOC_SCRATCH_BYTES (64u << 20)
+int wt_pair_build_noalloc(const void *d_text, uint64_t n, uint32_t sym_bytes, uint32_t lg_sigma, wt_levels *wt,
+                          wt_levels *wm, hipStream_t stream);
+
+/*
  * Construction by sorting (Section 3.2, construction using sorting,
  * Algorithm 2; the WM version of Section 5.1): the second build strategy,
  * with the same result as wt_build_tuned (levels, Z, directories, status).

@@ -26,6 +26,7 @@ WT_OK, WT_EINVAL, WT_ENOSPACE, WT_ERANGE, WT_EHIP, WT_ENOTSUP = 0, -1, -2, -3, -
 WT_MAX_TREE_LEVELS = 26
 WT_SEL_SPACING = 4096
 WT_NUM_KERNEL_IDS = 16
+WT_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it first (python __graft_entry__.py build or "
@@ -106,6 +107,7 @@ _SIGS = {
     "wt_pair_build": (_i, [_v, _u64, _u32, _u32, _LP, _LP, _v, _sz, _v]),
     "wt_pair_workspace_bytes_tuned": (_sz, [_u64, _u32, _u32, _TP]),
     "wt_pair_build_tuned": (_i, [_v, _u64, _u32, _u32, _LP, _LP, _v, _sz, _TP, _v]),
+    "wt_pair_build_noalloc": (_i, [_v, _u64, _u32, _u32, _LP, _LP, _v]),
     "wt_pair_build_recorded": (_i, [_v, _u64, _u32, _u32, _LP, _LP, _v, _sz, _v, ctypes.POINTER(_v),
                                     ctypes.POINTER(_u32), _u32, ctypes.POINTER(_u32)]),
     "wt_ps_workspace_bytes": (_sz, [_u64, _u32, _u32]),
@@ -297,6 +299,17 @@ def pair_build(d_text, n: int, sym_bytes: int, L: int, stream=None, ws=None, out
                                  ctypes.c_void_p(ws.data_ptr()), ws.numel(), _tune_ptr(tune), _stream_handle(stream))
     check(rc, "wt_pair_build")
     wt._ws = ws
+    return wt, wm
+
+
+def pair_build_noalloc(d_text, n: int, sym_bytes: int, L: int, out, stream=None):
+    """wt_pair_build_noalloc: both structures into out = (wt, wm), already
+    bound Structures, with the library's own per-GPU scratch as workspace (no
+    device allocation in the call)."""
+    wt, wm = out
+    ptr = ctypes.c_void_p(d_text.data_ptr() if n > 0 else 0)
+    check(wt_pair_build_noalloc(ptr, n, sym_bytes, L, ctypes.byref(wt.view), ctypes.byref(wm.view),
+                                _stream_handle(stream)), "wt_pair_build_noalloc")
     return wt, wm
 
 

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <vector>
 
@@ -478,6 +479,47 @@ int wt_pair_build_tuned(const void *d_text, uint64_t n, uint32_t sym_bytes, uint
 {
     LaunchCtx ctx{stream, nullptr, nullptr};
     return pair_one(d_text, n, sym_bytes, lg_sigma, wt, wm, d_ws, ws_bytes, tune, ctx);
+}
+
+}  // extern "C"
+
+// Workspace of the allocation-free pair build: a file-scope device array, one
+// copy per GPU (loaded with this file's code object, held until the process
+// ends).  In host code its name is only a host-side stand-in: the device
+// address of the current GPU's copy comes from hipGetSymbolAddress, taken
+// once per device and kept here; only that address is handed to kernels.
+static __device__ __align__(256) uint8_t scratch[WT_NOALLOC_SCRATCH_BYTES];
+static constexpr int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxScratchDevices];
+
+// address of the current device's scratch, or null if the runtime refuses
+static void *scratch_for_current_device()
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxScratchDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
+extern "C" {
+
+int wt_pair_build_noalloc(const void *d_text, uint64_t n, uint32_t sym_bytes, uint32_t lg_sigma, wt_levels *wt,
+                          wt_levels *wm, hipStream_t stream)
+{
+    // sizes are checked before the device is touched
+    const size_t need = pair_ws_bytes(n, sym_bytes, lg_sigma, nullptr);
+    if (need == 0) return WT_EINVAL;
+    if (need > (size_t)WT_NOALLOC_SCRATCH_BYTES) return WT_ENOSPACE;
+    void *ws = scratch_for_current_device();
+    if (!ws) return WT_EHIP;
+    LaunchCtx ctx{stream, nullptr, nullptr};
+    return pair_one(d_text, n, sym_bytes, lg_sigma, wt, wm, ws, (size_t)WT_NOALLOC_SCRATCH_BYTES, nullptr, ctx);
 }
 
 int wt_build(const void *d_text, uint64_t n, uint32_t sym_bytes, uint32_t lg_sigma,

@@ -26,6 +26,15 @@ def test_exports_every_declared_symbol():
         assert getattr(B.lib, n) is not None
 
 
+def test_binding_constants_match_header():
+    from paper_1702_07578_amd import binding as B
+    src = open(os.path.join(ROOT, "include", "wt.h")).read()
+    m = re.search(r"#define WT_NOALLOC_SCRATCH_BYTES \((\d+)u << (\d+)\)", src)
+    assert m and int(m.group(1)) << int(m.group(2)) == B.WT_NOALLOC_SCRATCH_BYTES
+    m = re.search(r"#define WT_MAX_TREE_LEVELS (\d+)", src)
+    assert m and int(m.group(1)) == B.WT_MAX_TREE_LEVELS
+
+
 def test_sizes_and_bind():
     from paper_1702_07578_amd import binding as B
     for n, L in ((0, 0), (10, 3), (1000, 8), (1 << 20, 8), (123457, 20)):
@@ -60,6 +69,10 @@ def test_argument_errors_return_before_device_work():
     assert B.wm_build(fake, 100, 1, 4, ctypes.byref(v), fake, 1 << 20, None) == B.WT_EINVAL
     assert B.wt_access(None, fake, 1, fake, None) == B.WT_EINVAL
     assert B.wt_strerror(B.WT_ERANGE).decode().startswith("symbol")
+    # the allocation-free pair build checks sizes before it looks for a device
+    assert B.wt_pair_workspace_bytes(1 << 26, 2, 16) > B.WT_NOALLOC_SCRATCH_BYTES
+    assert B.wt_pair_build_noalloc(fake, 1 << 26, 2, 16, ctypes.byref(v), ctypes.byref(v), None) == B.WT_ENOSPACE
+    assert B.wt_pair_build_noalloc(fake, 100, 3, 3, ctypes.byref(v), ctypes.byref(v), None) == B.WT_EINVAL
 
 
 def test_conversion_and_position_map_sizes():
