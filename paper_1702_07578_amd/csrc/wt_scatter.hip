@@ -351,6 +351,102 @@ __device__ __attribute__((always_inline)) inline void split_pass(uint32_t (&v)[k
     if (lane < kChunks) sm.bits[a][lane] = ((uint64_t)acc_hi << 32) | acc_lo;
 }
 
+// The split of a byte tile, with every lane owning runs of 8 consecutive
+// positions: block b (of 4) of the tile order holds positions [512 b, 512 b +
+// 512), and lane l holds positions 512 b + 8 l + j, j = 0..7, as two 32-bit
+// words of four symbols.  Per block a lane then knows the bits of its own 8
+// positions: they form one byte of level a's word stream (byte 64 b + l), and
+// its ones before each of them come from a count of its own plus a wave scan
+// of the lanes' counts.  A symbol at position p with r ones before it in the
+// tile goes to base1 + r when its bit is one and to p - r when it is zero
+// (base1 = zeros of the bit in the tile).
+
+// One symbol of a lane's run: VCC := its bit (byte j of the flag word f is
+// nonzero); the zero's place is K - X1 + i (K > X1 always; v_sad_u32 gives
+// |K - X1| + i); dest := bit ? X1 : that; X1 += bit.  VCC is the only scalar
+// register written; the sad sits between the compare and the first read of
+// VCC, which gives the one wait state a vector read of a vector-written
+// scalar register needs on this chip.
+template <uint32_t J, uint32_t I>
+__device__ __attribute__((always_inline)) inline uint32_t split_step(uint32_t f, uint32_t K, uint32_t &X1)
+{
+    uint32_t d;
+    asm volatile(
+        "v_cmp_ne_u32_sdwa vcc, %[f], 0 src0_sel:BYTE_%c[j] src1_sel:DWORD\n\t"
+        "v_sad_u32 %[d], %[K], %[x], %[i]\n\t"
+        "v_cndmask_b32_e32 %[d], %[d], %[x], vcc\n\t"
+        "v_addc_co_u32_e32 %[x], vcc, 0, %[x], vcc"
+        : [d] "=&v"(d), [x] "+v"(X1)
+        : [f] "v"(f), [K] "v"(K), [j] "n"(J), [i] "n"(I)
+        : "vcc");
+    return d;
+}
+
+// Ballots (SPLIT false) or split (SPLIT true) of a byte tile by bit bp of the
+// symbols; level a's word stream goes to sm.bits[a].  Returns nothing; the
+// tile's zero count of the bit comes from its own count, not from a table.
+template <typename E, bool REORDER, bool PAIR, uint32_t KB, bool SPLIT>
+__device__ __attribute__((always_inline)) inline void split_pass_bytes(uint32_t a, uint32_t bp,
+                                                                       WaveSmem<E, REORDER, PAIR, KB> &sm)
+{
+    static_assert(sizeof(E) == 1 && kWaveTile == 2048, "byte tiles of 4 blocks of 512");
+    typedef __attribute__((address_space(3))) uint8_t lds_u8;
+    const uint32_t lane = lane_id();
+    const uint32_t ebase = (uint32_t)(uintptr_t)(lds_u8 *)sm.elem;
+    uint32_t q[8];
+#pragma unroll
+    for (uint32_t b = 0; b < 4; b++) {
+        const uint2 u = *(const uint2 *)(sm.elem + 512 * b + 8 * lane);
+        q[2 * b] = u.x;
+        q[2 * b + 1] = u.y;
+    }
+    // bits past the symbol width (a byte text with more than 8 levels) are 0
+    const uint32_t mask = bp < 8 ? 0x01010101u << bp : 0u;
+    uint32_t f[8];
+#pragma unroll
+    for (uint32_t d = 0; d < 8; d++) f[d] = q[d] & mask;
+    // the lane's byte of the level word in each block, and its count
+    uint32_t cnt[4];
+    lds_u8 *lvl = (lds_u8 *)(uintptr_t)(uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint64_t *)sm.bits[a];
+#pragma unroll
+    for (uint32_t b = 0; b < 4; b++) {
+        const uint32_t w = __builtin_amdgcn_udot4(
+                               f[2 * b], 0x08040201u,
+                               __builtin_amdgcn_udot4(f[2 * b + 1], 0x80402010u, 0u, false), false) >> (bp & 7);
+        cnt[b] = __builtin_popcount(w);
+        lvl[64 * b + lane] = (uint8_t)w;
+    }
+    if (!SPLIT) return;
+    // ones before the lane's run of each block: two scans of 16-bit pairs
+    const uint32_t c01 = cnt[0] | (cnt[1] << 16), c23 = cnt[2] | (cnt[3] << 16);
+    const uint32_t i01 = wave_incl_scan(c01), i23 = wave_incl_scan(c23);
+    const uint32_t t01 = last_lane(i01), t23 = last_lane(i23);
+    const uint32_t e01 = i01 - c01, e23 = i23 - c23;
+    const uint32_t T0 = t01 & 0xFFFFu, T01 = T0 + (t01 >> 16), T012 = T01 + (t23 & 0xFFFFu);
+    const uint32_t ones = T012 + (t23 >> 16);
+    const uint32_t P1[4] = {e01 & 0xFFFFu, T0 + (e01 >> 16), T01 + (e23 & 0xFFFFu), T012 + (e23 >> 16)};
+    // base1 = zeros of the bit; ones go to ebase + base1 + (ones before)
+    const uint32_t X1base = ebase + (kWaveTile - ones);
+    // everything the lane reads is loaded; the writes below may overwrite it
+    wave_sync();
+#pragma unroll
+    for (uint32_t b = 0; b < 4; b++) {
+        uint32_t X1 = X1base + P1[b];
+        const uint32_t K = X1base + ebase + 512 * b + 8 * lane;
+        const uint32_t fa = f[2 * b], fb = f[2 * b + 1], qa = q[2 * b], qb = q[2 * b + 1];
+        const uint32_t sa = qa >> 8, sb = qb >> 8;
+        uint32_t dd;
+        dd = split_step<0, 0>(fa, K, X1); *(lds_u8 *)(uintptr_t)dd = (uint8_t)qa;
+        dd = split_step<1, 1>(fa, K, X1); *(lds_u8 *)(uintptr_t)dd = (uint8_t)sa;
+        dd = split_step<2, 2>(fa, K, X1); *(lds_u8 *)(uintptr_t)dd = (uint8_t)(qa >> 16);
+        dd = split_step<3, 3>(fa, K, X1); *(lds_u8 *)(uintptr_t)dd = (uint8_t)(sa >> 16);
+        dd = split_step<0, 4>(fb, K, X1); *(lds_u8 *)(uintptr_t)dd = (uint8_t)qb;
+        dd = split_step<1, 5>(fb, K, X1); *(lds_u8 *)(uintptr_t)dd = (uint8_t)sb;
+        dd = split_step<2, 6>(fb, K, X1); *(lds_u8 *)(uintptr_t)dd = (uint8_t)(qb >> 16);
+        dd = split_step<3, 7>(fb, K, X1); *(lds_u8 *)(uintptr_t)dd = (uint8_t)(sb >> 16);
+    }
+}
+
 // One tile of kWaveTile symbols (the text's last tile may be shorter; it is
 // padded).
 // 16-byte units of a whole tile per lane, and the tile's units as loaded by
@@ -477,22 +573,32 @@ __device__ __attribute__((always_inline)) inline void wave_tile(const TextDesc &
     // 4. split by one bit at a time; the ballots are the levels.  The zeros
     //    of bit a in the tile: the start of the first key whose bit a is one,
     //    in the order of level a + 1.
-    uint32_t v[kChunks];
-#pragma unroll
-    for (uint32_t c = 0; c < kChunks; c++) v[c] = sm.elem[c * 64 + lane];
-    wave_sync();
-    for (uint32_t a = 0; a + 1 < Kg; a++) {
-        split_pass<E, REORDER, PAIR, KB, true>(v, a, 1u << (shift + Kg - 1 - a), sm.lo[lvl_off(a + 1) + 1], sm);
+    if constexpr (sizeof(E) == 1) {
+        for (uint32_t a = 0; a + 1 < Kg; a++) {
+            split_pass_bytes<E, REORDER, PAIR, KB, true>(a, shift + Kg - 1 - a, sm);
+            wave_sync();
+        }
+        split_pass_bytes<E, REORDER, PAIR, KB, REORDER>(Kg - 1, shift, sm);
         wave_sync();
+    }
+    uint32_t v[kChunks];
+    if constexpr (sizeof(E) != 1) {
 #pragma unroll
         for (uint32_t c = 0; c < kChunks; c++) v[c] = sm.elem[c * 64 + lane];
         wave_sync();
+        for (uint32_t a = 0; a + 1 < Kg; a++) {
+            split_pass<E, REORDER, PAIR, KB, true>(v, a, 1u << (shift + Kg - 1 - a), sm.lo[lvl_off(a + 1) + 1], sm);
+            wave_sync();
+#pragma unroll
+            for (uint32_t c = 0; c < kChunks; c++) v[c] = sm.elem[c * 64 + lane];
+            wave_sync();
+        }
     }
     if (REORDER) {
         // the last split orders the tile by its reversed Kg-bit key: each
         // key's symbols, in text order, go to the key's place in the next
         // group's sequence (padding sorts last and is dropped)
-        split_pass<E, REORDER, PAIR, KB, true>(v, Kg - 1, 1u << shift, sm.loK[1], sm);
+        if constexpr (sizeof(E) != 1) split_pass<E, REORDER, PAIR, KB, true>(v, Kg - 1, 1u << shift, sm.loK[1], sm);
         wave_sync();
         E *gout = (E *)seq_out(d, g);
         for (uint32_t p = lane; p < len; p += 64) {
@@ -502,7 +608,7 @@ __device__ __attribute__((always_inline)) inline void wave_tile(const TextDesc &
             if (gi < d.n) gout[gi] = x;
         }
     } else {
-        split_pass<E, REORDER, PAIR, KB, false>(v, Kg - 1, 1u << shift, 0u, sm);
+        if constexpr (sizeof(E) != 1) split_pass<E, REORDER, PAIR, KB, false>(v, Kg - 1, 1u << shift, 0u, sm);
     }
     wave_sync();
 
