@@ -39,6 +39,7 @@ struct WaveSmem {
     static constexpr uint32_t kKeysB = 1u << KB;        // keys of level KB (the finest)
     static constexpr uint32_t kWordsB = KB * kChunks;   // full output words of one tile
     static constexpr uint32_t kScanPer = (kKeysB + 63) / 64;  // table entries per lane in a scan
+    static_assert(kRunsB <= 256, "a run index fits one byte");
     // level a of the tile in order a; while the tables are built (and at a
     // range start) it holds the finest key counts and their prefix sums
     uint64_t bits[KB][kChunks];
@@ -57,8 +58,13 @@ struct WaveSmem {
     union alignas(16) {
         E elem[kWaveTile];  // the tile, in its next order (loading and splits)
         struct {            // copy-out, after the splits
-            uint16_t kw[kWordsB];  // run of every full word
+            uint8_t kw[kWordsB];   // run of every full word
             uint16_t wb[kRunsB];   // first full word of every run, all levels
+            // per run: its first full word's bit in the level streams and
+            // its word on the output, each minus (64 or 1) x its first word
+            // number, so that word q of the numbering takes bit rec.x + 64 q
+            // to word rec.y + q
+            uint2 rec[kRunsB];
         } co;
     };
 
@@ -104,15 +110,19 @@ __device__ inline uint32_t wave_exscan_n(uint32_t n, Get get, Put put)
 // level of table entry e (entries lvl_off(a) .. lvl_off(a+1)-1 are level a)
 __device__ inline uint32_t level_of(uint32_t e) { return 31 - __clz(e + 1); }
 
-// cnt (<= 64) bits of level a starting at tile-order bit s
-__device__ inline uint64_t stream_bits(const uint64_t *src, uint32_t s, uint32_t cnt)
+// The 64 bits of the tile's level streams starting at bit s (all levels in
+// one array, level a at bit a * kWaveTile): three 32-bit words and two
+// funnel shifts.  The third word is read only to be shifted out when s is a
+// multiple of 32; reads past the last level stay inside the wave's LDS.
+__device__ inline uint64_t stream64(const uint64_t *levels, uint32_t s)
 {
-    const uint32_t sh = s & 63;
-    uint64_t x = src[s >> 6] >> sh;
-    if (sh + cnt > 64) x |= src[(s >> 6) + 1] << (64 - sh);
-    if (cnt < 64) x &= (1ull << cnt) - 1;
-    return x;
+    const uint32_t *w = (const uint32_t *)levels + (s >> 5);
+    const uint32_t d0 = w[0], d1 = w[1], d2 = w[2], sh = s & 31;
+    return ((uint64_t)__builtin_amdgcn_alignbit(d2, d1, sh) << 32) | __builtin_amdgcn_alignbit(d1, d0, sh);
 }
+
+// the low cnt bits of x, 0 < cnt <= 64
+__device__ inline uint64_t low_bits(uint64_t x, uint32_t cnt) { return x & (~0ull >> (64 - cnt)); }
 
 // f(integral_constant<I>) for I = B .. N-1, unrolled at compile time
 template <uint32_t I, uint32_t N, typename F>
@@ -187,16 +197,13 @@ __device__ inline void wave_range_start(const TextDesc &d, uint32_t g, uint32_t 
     wave_sync();
 }
 
-// full words of a run: [ceil(G/64), floor((G+h)/64))
-__device__ inline uint32_t full_words(uint32_t gs, uint32_t hh)
+// full words of a run: [ceil(G/64), floor((G+h)/64)), none past word W
+__device__ inline uint32_t full_words(uint32_t gs, uint32_t hh, uint32_t W)
 {
-    const uint32_t f = (gs + 63) >> 6, l = (uint32_t)(((uint64_t)gs + hh) >> 6);
+    const uint32_t f = (gs + 63) >> 6, l = min((uint32_t)(((uint64_t)gs + hh) >> 6), W);
     return l > f ? l - f : 0u;
 }
 
-// Words that a run of this tile covers completely, all levels at once, by
-// plain stores: the full words of all runs are numbered run by run, and the
-// lanes take consecutive words.
 // One output of the scatter: the global starts of the runs, the words kept
 // at run ends, and the base of the group's bit vectors.
 struct Side {
@@ -206,6 +213,9 @@ struct Side {
     uint64_t *base;
 };
 
+// Words that a run of this tile covers completely, all levels at once, by
+// plain stores: the full words of all runs are numbered run by run, and the
+// lanes take consecutive words.
 template <typename E, bool REORDER, bool PAIR, uint32_t KB>
 __device__ __attribute__((always_inline)) inline void copy_full_words(const TextDesc &d, uint32_t Kg,
                                                                       WaveSmem<E, REORDER, PAIR, KB> &sm,
@@ -214,14 +224,20 @@ __device__ __attribute__((always_inline)) inline void copy_full_words(const Text
     const uint32_t lane = lane_id();
     const uint32_t nr = lvl_off(Kg);
     const uint32_t *G = sd.G;
+    const uint32_t W = (uint32_t)d.W;
     const uint32_t total = wave_exscan_n<WaveSmem<E, REORDER, PAIR, KB>::kScanPer>(
-        nr, [&](uint32_t e) { return full_words(G[e], sm.h[e]); },
-        [&](uint32_t e, uint32_t x) { sm.co.wb[e] = (uint16_t)x; });
+        nr, [&](uint32_t e) { return full_words(G[e], sm.h[e], W); },
+        [&](uint32_t e, uint32_t x) {
+            const uint32_t a = level_of(e), gs = G[e], gw = (gs + 63) >> 6;
+            sm.co.wb[e] = (uint16_t)x;
+            sm.co.rec[e] = make_uint2(a * kWaveTile + sm.lo[e] + ((gw << 6) - gs) - 64u * x,
+                                      sm.lvw[a] + gw - x);
+        });
     // run of every word: the run whose first word it is, carried forward
     for (uint32_t q = lane; q < total; q += 64) sm.co.kw[q] = 0;
     wave_sync();
     for (uint32_t e = lane; e < nr; e += 64)
-        if (full_words(G[e], sm.h[e]) != 0) sm.co.kw[sm.co.wb[e]] = (uint16_t)e;
+        if (full_words(G[e], sm.h[e], W) != 0) sm.co.kw[sm.co.wb[e]] = (uint8_t)e;
     wave_sync();
     constexpr uint32_t PER = (KB * kChunks + 63) / 64;
     uint32_t m = 0;
@@ -238,17 +254,14 @@ __device__ __attribute__((always_inline)) inline void copy_full_words(const Text
         const uint32_t q = lane * PER + i;
         if (q < total) {
             run = max(run, (uint32_t)sm.co.kw[q]);
-            sm.co.kw[q] = (uint16_t)run;
+            sm.co.kw[q] = (uint8_t)run;
         }
     }
     wave_sync();
     uint64_t *base = sd.base;
-    const uint32_t W = (uint32_t)d.W;
     for (uint32_t q = lane; q < total; q += 64) {
-        const uint32_t e = sm.co.kw[q], a = level_of(e);
-        const uint32_t gs = G[e];
-        const uint32_t gw = ((gs + 63) >> 6) + (q - sm.co.wb[e]);
-        if (gw < W) base[sm.lvw[a] + gw] = stream_bits(sm.bits[a], sm.lo[e] + ((gw << 6) - gs), 64);
+        const uint2 r = sm.co.rec[sm.co.kw[q]];
+        base[r.y + q] = stream64(&sm.bits[0][0], r.x + 64u * q);
     }
     wave_sync();
 }
@@ -267,39 +280,31 @@ __device__ __attribute__((always_inline)) inline void run_end_words(const TextDe
         const uint32_t hh = sm.h[e];
         if (hh == 0) continue;
         const uint32_t a = level_of(e);
-        uint64_t *out = base + sm.lvw[a];
-        const uint64_t *src = sm.bits[a];
-        const uint32_t ls = sm.lo[e];
+        const uint32_t sb = a * kWaveTile + sm.lo[e];  // the run's first bit in the streams
         // positions are below n < 2^32; ge may equal n
         const uint32_t gs = sd.G[e], ge = gs + hh;
         const uint32_t fw = gs >> 6, lw = (ge - 1) >> 6;
         const uint32_t off = gs & 63;
-        uint8_t newp = kNoPend;
-        uint64_t newv = 0;
-        if (off != 0 || hh < 64) {
-            const uint32_t cnt = min(hh, 64u - off);  // bits of the run in word fw
-            uint64_t val = stream_bits(src, ls, cnt) << off;
-            bool lowok = off == 0;
-            const uint8_t pw = sd.pend[e];
-            if (!lowok && pw != kNoPend) {  // the kept word is fw
-                val |= sd.pend_v[e];
-                lowok = pw == kPend;
-            }
-            if (off + cnt == 64) {
-                if (fw >= W) continue;  // never for consistent tables
-                if (lowok) out[fw] = val;
-                else atomicOr((unsigned long long *)&out[fw], (unsigned long long)val);
-            } else {
-                newp = lowok ? kPend : kPendForeign;
-                newv = val;
-            }
+        // the first word, when the run does not cover it from its bit 0
+        // to its top (the full words are stored by copy_full_words)
+        const bool head = off != 0 || hh < 64;
+        const uint32_t cnt = min(hh, 64u - off);  // bits of the run in word fw
+        uint64_t hv = low_bits(stream64(&sm.bits[0][0], sb), cnt) << off;
+        const uint8_t pw = sd.pend[e];
+        const bool merge = off != 0 && pw != kNoPend;  // the kept word is fw
+        if (merge) hv |= sd.pend_v[e];
+        const bool lowok = off == 0 || pw == kPend;
+        const bool head_full = off + cnt == 64;
+        if (head && head_full && fw < W) {
+            if (lowok) base[sm.lvw[a] + fw] = hv;
+            else atomicOr((unsigned long long *)&base[sm.lvw[a] + fw], (unsigned long long)hv);
         }
-        if (lw != fw && (ge & 63) != 0 && lw < W) {
-            newp = kPend;
-            newv = stream_bits(src, ls + ((lw << 6) - gs), ge & 63);
-        }
-        sd.pend[e] = newp;
-        sd.pend_v[e] = newv;
+        // the last word, when it is not the first and the run ends inside it
+        const bool tail = lw != fw && (ge & 63) != 0;
+        const uint64_t tv = low_bits(stream64(&sm.bits[0][0], sb + ((lw << 6) - gs)), (ge - 1) % 64 + 1);
+        const bool keep_head = head && !head_full;
+        sd.pend[e] = tail ? kPend : (keep_head ? (lowok ? kPend : kPendForeign) : kNoPend);
+        sd.pend_v[e] = tail ? tv : (keep_head ? hv : 0ull);
     }
 }
 
@@ -684,12 +689,14 @@ constexpr uint32_t scat_block_waves()
 
 // Waves per SIMD the registers are held to: the byte-symbol pair kernel with
 // 7-level tables (7.5 KiB of LDS) to five, where only values used by a padded
-// last tile spill; the re-ordering pair kernel of 1- and 2-byte symbols to
-// three.  The others keep the compiler's choice.
+// last tile spill; the single byte-symbol kernel to four (its LDS allows four);
+// the re-ordering pair kernel of 1- and 2-byte symbols to three.  The others
+// keep the compiler's choice.
 template <typename E, bool REORDER, bool PAIR, uint32_t KB>
-constexpr uint32_t kScatMinWaves = (sizeof(E) == 1 && PAIR && !REORDER && KB == 7) ? 5
-                                   : (PAIR && REORDER && sizeof(E) <= 2)          ? 3
-                                                                                  : 1;
+constexpr uint32_t kScatMinWaves = (sizeof(E) == 1 && PAIR && !REORDER && KB == 7)   ? 5
+                                   : (sizeof(E) == 1 && !PAIR && !REORDER)            ? 4
+                                   : (PAIR && REORDER && sizeof(E) <= 2)              ? 3
+                                                                                      : 1;
 
 // Work item = (text, range); wave w of workgroup b takes item b BW + w,
 // then strides by the whole grid.  The REORDER variant takes the texts whose
