@@ -493,8 +493,11 @@ __device__ __attribute__((always_inline)) inline void wave_tile(const TextDesc &
 
     // 1. the tile, in text order, through registers into LDS, counting the
     //    finest keys by LDS atomics on the way (the registers are free while
-    //    the tables are built)
-    for (uint32_t k = lane; k < nk; k += 64) cnt[k] = 0;
+    //    the tables are built).  With few keys, each key has 2^cb copies of
+    //    its counter (lane l adds to copy l mod 2^cb), so that the lanes of
+    //    one atomic instruction do not all meet on a handful of words.
+    const uint32_t cb = min(4u, KB - Kg), lane_copy = lane & ((1u << cb) - 1u);
+    for (uint32_t k = lane; k < (nk << cb); k += 64) cnt[k] = 0;
     wave_sync();
     if (!padded && vec) {
         // whole tile of a 16-byte aligned sequence: 16-byte units; with
@@ -514,7 +517,7 @@ __device__ __attribute__((always_inline)) inline void wave_tile(const TextDesc &
             for (uint32_t j = 0; j < 4; j++)
 #pragma unroll
                 for (uint32_t s = 0; s < 4 / sizeof(E); s++)
-                    atomicAdd(&cnt[__builtin_amdgcn_ubfe(w4[j], s * width + ks, kw)], 1u);
+                    atomicAdd(&cnt[(__builtin_amdgcn_ubfe(w4[j], s * width + ks, kw) << cb) | lane_copy], 1u);
         }
         if (kPrefetch<E>) {
             // the next tile of the range, when it is whole
@@ -527,14 +530,14 @@ __device__ __attribute__((always_inline)) inline void wave_tile(const TextDesc &
 #pragma unroll
             for (uint32_t c = 0; c < kChunks; c++) v[c] = src[c * 64];
 #pragma unroll
-            for (uint32_t c = 0; c < kChunks; c++) atomicAdd(&cnt[(v[c] >> shift) & kmask], 1u);
+            for (uint32_t c = 0; c < kChunks; c++) atomicAdd(&cnt[(((v[c] >> shift) & kmask) << cb) | lane_copy], 1u);
         } else {
 #pragma unroll
             for (uint32_t c = 0; c < kChunks; c++)
                 v[c] = (c * 64 + lane < len) ? (uint32_t)src[c * 64] : (uint32_t)(E)~0u;
 #pragma unroll
             for (uint32_t c = 0; c < kChunks; c++)
-                if (c * 64 + lane < len) atomicAdd(&cnt[(v[c] >> shift) & kmask], 1u);
+                if (c * 64 + lane < len) atomicAdd(&cnt[(((v[c] >> shift) & kmask) << cb) | lane_copy], 1u);
         }
 #pragma unroll
         for (uint32_t c = 0; c < kChunks; c++) sm.elem[c * 64 + lane] = (E)v[c];
@@ -543,11 +546,17 @@ __device__ __attribute__((always_inline)) inline void wave_tile(const TextDesc &
 
     // 2. the tile's count of every key of levels 0..Kg-1, as differences of
     //    the prefix sums P of the finest counts (padding not counted)
+    // (a key's count: the sum of its copies)
+    auto key_count = [&](uint32_t k) {
+        uint32_t x = 0;
+        for (uint32_t c = 0; c < (1u << cb); c++) x += cnt[(k << cb) + c];
+        return x;
+    };
     wave_exscan_n<WaveSmem<E, REORDER, PAIR, KB>::kScanPer>(
-        nk, [&](uint32_t k) { return cnt[k]; }, [&](uint32_t k, uint32_t x) { P[k] = (uint16_t)x; });
+        nk, key_count, [&](uint32_t k, uint32_t x) { P[k] = (uint16_t)x; });
     if (lane == 0) P[nk] = (uint16_t)len;
     if (REORDER)
-        for (uint32_t k = lane; k < nk; k += 64) sm.hK[k] = (uint16_t)cnt[k];
+        for (uint32_t k = lane; k < nk; k += 64) sm.hK[k] = (uint16_t)key_count(k);
     wave_sync();
     for (uint32_t e = lane; e < lvl_off(Kg); e += 64) {
         const uint32_t a = level_of(e), k = e - lvl_off(a), sh = Kg - a;
