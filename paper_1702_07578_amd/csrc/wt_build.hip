@@ -52,12 +52,14 @@ __global__ void k_init_batch(const TextDesc *__restrict__ descs, uint32_t nd)
 // Each lane reads 16-byte units of the range; units past the range end are
 // read symbol by symbol.
 
-constexpr uint32_t kHistCopies = 8;
+// counters per wave in the histogram's shared array: 2^11, eight copies of
+// each of 256 keys
+constexpr uint32_t kHistLog2PerWave = 11;
 
 // himask: the bits at or above L of every symbol in a 32-bit word (0 when no
 // check is needed); key of a symbol: its bits from `shift` up, kw of them
 // (the key's bits above the symbol's width are zero)
-template <typename E>
+template <typename E, uint32_t lc>
 __device__ inline void count_unit(const uint4 &u, uint32_t shift, uint32_t kw, uint32_t himask,
                                   bool &bad, uint32_t *hist)
 {
@@ -67,26 +69,28 @@ __device__ inline void count_unit(const uint4 &u, uint32_t shift, uint32_t kw, u
         bad |= (w4[q] & himask) != 0;
 #pragma unroll
         for (uint32_t s = 0; s < 4 / sizeof(E); s++)
-            atomicAdd(&hist[__builtin_amdgcn_ubfe(w4[q], s * 8 * sizeof(E) + shift, kw) * kHistCopies], 1u);
+            atomicAdd(&hist[__builtin_amdgcn_ubfe(w4[q], s * 8 * sizeof(E) + shift, kw) << lc], 1u);
     }
 }
 
-template <typename E>
+template <typename E, uint32_t lc>
 __device__ void hist_range(const TextDesc &d, uint32_t g, uint32_t Kg, uint32_t r, uint32_t *sh)
 {
     const uint32_t tid = threadIdx.x, w = tid >> 6;
     const uint32_t nk = 1u << Kg, mask = nk - 1u;
-    // every wave counts into kHistCopies interleaved copies (copy = lane mod
-    // kHistCopies), so lanes with equal keys mostly hit different words in
-    // different banks
+    // every wave counts into 2^lc interleaved copies of each key (copy = lane
+    // mod 2^lc), so lanes with equal keys mostly hit different words in
+    // different banks: 8 copies for 64 keys or more (measured best for 128
+    // and 256 keys), one per lane for 32 keys or fewer
+    const uint32_t per_wave = nk << lc;
     const uint32_t shift = d.L - g * d.K - Kg;
     const uint64_t span = (uint64_t)d.R << d.log2S;
     const uint64_t start = (uint64_t)r * span;
     const uint64_t len = min(span, d.n - start);
     const E *src = (const E *)seq_in(d, g) + start;
-    uint32_t *hist = sh + w * nk * kHistCopies + (tid & (kHistCopies - 1));
+    uint32_t *hist = sh + w * per_wave + (tid & ((1u << lc) - 1u));
 
-    for (uint32_t i = tid; i < kTileWaves * nk * kHistCopies; i += kTileThreads) sh[i] = 0;
+    for (uint32_t i = tid; i < kTileWaves * per_wave; i += kTileThreads) sh[i] = 0;
     __syncthreads();
     bool bad = false;
     const bool check = (g == 0) && (d.L < 32);
@@ -110,49 +114,76 @@ __device__ void hist_range(const TextDesc &d, uint32_t g, uint32_t Kg, uint32_t 
         for (; i + 3 * kTileThreads < nu; i += 4 * kTileThreads) {
             const uint4 a0 = u[i], a1 = u[i + kTileThreads], a2 = u[i + 2 * kTileThreads],
                         a3 = u[i + 3 * kTileThreads];
-            count_unit<E>(a0, kshift, kw, himask, bad, hist);
-            count_unit<E>(a1, kshift, kw, himask, bad, hist);
-            count_unit<E>(a2, kshift, kw, himask, bad, hist);
-            count_unit<E>(a3, kshift, kw, himask, bad, hist);
+            count_unit<E, lc>(a0, kshift, kw, himask, bad, hist);
+            count_unit<E, lc>(a1, kshift, kw, himask, bad, hist);
+            count_unit<E, lc>(a2, kshift, kw, himask, bad, hist);
+            count_unit<E, lc>(a3, kshift, kw, himask, bad, hist);
         }
-        for (; i < nu; i += kTileThreads) count_unit<E>(u[i], kshift, kw, himask, bad, hist);
+        for (; i < nu; i += kTileThreads) count_unit<E, lc>(u[i], kshift, kw, himask, bad, hist);
         done = nu * per_unit;
     }
     for (uint64_t i = done + tid; i < len; i += kTileThreads) {
         const uint32_t e = src[i];
         if (check && (e >> d.L) != 0) bad = true;
-        atomicAdd(&hist[((e >> shift) & mask) * kHistCopies], 1u);
+        atomicAdd(&hist[((e >> shift) & mask) << lc], 1u);
     }
     if (bad) {
         atomicExch(d.status, (int32_t)WT_ERANGE);
         if (d.pair) atomicExch(d.status2, (int32_t)WT_ERANGE);
     }
     __syncthreads();
+    // sum every key's copies in all waves: thread (k, p), p < P = threads
+    // per key, adds every P-th of them; the P parts are then halved in place
+    // until one is left
     uint32_t *H = d.H + (uint64_t)r * nk;
-    for (uint32_t k = tid; k < nk; k += kTileThreads) {
-        uint32_t s = 0;
+    if (lc == 3) {  // 64 keys or more: one thread sums all copies of a key
+        for (uint32_t k = tid; k < nk; k += kTileThreads) {
+            uint32_t t = 0;
 #pragma unroll
-        for (uint32_t ww = 0; ww < kTileWaves; ww++)
-#pragma unroll
-            for (uint32_t cp = 0; cp < kHistCopies; cp++) s += sh[(ww * nk + k) * kHistCopies + cp];
-        H[k] = s;
+            for (uint32_t j = 0; j < (kTileWaves << lc); j++) t += sh[(j >> lc) * per_wave + (k << lc) + (j & 7)];
+            H[k] = t;
+        }
+        return;
     }
+    const uint32_t P = kTileThreads / nk, k = tid % nk, p = tid / nk;
+    const uint32_t J = kTileWaves << lc;  // counters of one key
+    uint32_t part = 0;
+    for (uint32_t j = p; j < J; j += P) part += sh[(j >> lc) * per_wave + (k << lc) + (j & ((1u << lc) - 1u))];
+    if (P == 1) {
+        H[k] = part;
+        return;
+    }
+    __syncthreads();
+    sh[tid] = part;  // part p of key k at p nk + k
+    __syncthreads();
+    for (uint32_t half = P >> 1; half > 0; half >>= 1) {
+        if (tid < half * nk) sh[tid] += sh[tid + half * nk];
+        __syncthreads();
+    }
+    if (tid < nk) H[tid] = sh[tid];
 }
 
 __global__ __launch_bounds__(kTileThreads) void k_hist(const TextDesc *__restrict__ descs,
                                                        const uint32_t *__restrict__ bases,
                                                        uint32_t nd, uint32_t nitems, uint32_t g)
 {
-    __shared__ uint32_t sh[kTileWaves * (1u << kMaxGroupBits) * kHistCopies];
+    __shared__ uint32_t sh[kTileWaves << kHistLog2PerWave];
     for (uint32_t item = blockIdx.x; item < nitems; item += gridDim.x) {
         const uint32_t ti = find_text(bases, nd, item);
         const TextDesc &d = descs[ti];
         const uint32_t r = item - item_base(bases, nd, ti);
         if (g >= d.G || r >= d.nranges) continue;
         const uint32_t Kg = group_bits(d, g);
-        if (d.b == 1) hist_range<uint8_t>(d, g, Kg, r, sh);
-        else if (d.b == 2) hist_range<uint16_t>(d, g, Kg, r, sh);
-        else hist_range<uint32_t>(d, g, Kg, r, sh);
+        static_assert(kMaxGroupBits + 3 <= kHistLog2PerWave && 5 + 6 <= kHistLog2PerWave, "copies fit");
+        if (Kg >= 6) {
+            if (d.b == 1) hist_range<uint8_t, 3>(d, g, Kg, r, sh);
+            else if (d.b == 2) hist_range<uint16_t, 3>(d, g, Kg, r, sh);
+            else hist_range<uint32_t, 3>(d, g, Kg, r, sh);
+        } else {
+            if (d.b == 1) hist_range<uint8_t, 6>(d, g, Kg, r, sh);
+            else if (d.b == 2) hist_range<uint16_t, 6>(d, g, Kg, r, sh);
+            else hist_range<uint32_t, 6>(d, g, Kg, r, sh);
+        }
         __syncthreads();
     }
 }
