@@ -93,6 +93,164 @@ def cpu_baseline(text, L, sample_n):
                       f"(levels and Z) in {dt:.2f} s"}
 
 
+def host_info():
+    """CPU model and core counts of the host the CPU baselines run on."""
+    model = "unknown"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
+def cpu_baseline_all_cores(text, L, sample_n):
+    """The oracle's top-down builder parallelised over every thread OpenMP
+    offers (the per-thread counts and interleaved prefix sum of Section 3.2
+    applied to each level's split), on a bounded prefix of the text."""
+    import oracle
+    orc = oracle.load()
+    s = text[:sample_n]
+    threads = orc.par_threads()
+    orc.par_build(1, s[: min(sample_n, 1 << 20)], L)  # warm the thread pool
+    t0 = time.perf_counter()
+    orc.par_build(1, s, L)
+    orc.par_build(0, s, L)
+    dt = time.perf_counter() - t0
+    return {"value": 2 * sample_n / dt, "unit": "symbols/s", "cores": threads, "kind": "oracle (all cores)",
+            "sample": f"first {sample_n} symbols of the same text, one WM and one WT build (levels and Z) "
+                      f"with {threads} threads in {dt:.2f} s"}
+
+
+# The paper's own construction times (Table 3: wavelet matrix, times in seconds,
+# median of five runs, without rank/select support), for the rows whose texts the
+# synthetic workloads stand in for.  Its hardware: two Intel Xeon E5-2686 v4 (up
+# to 32 of their cores used), 256 GB RAM, g++ 6.2 -O3, OpenMP 4.5 (Section 4).
+PAPER_TABLE3 = {
+    "hardware": "2x Intel Xeon E5-2686 v4, up to 32 cores used, 256 GB RAM (Section 4)",
+    "what": "wavelet matrix construction time in seconds, without rank/select (Table 3)",
+    "rows": {
+        "XML (n=2.9e8, sigma=97; markov96 stands in)": {
+            "n": 2.9e8, "pcWM_1core_s": 4.737, "pcWM_32core_s": 0.988, "psWM_1core_s": 4.355,
+            "psWM_32core_s": 0.531, "ddpcWM_32core_s": 0.468},
+        "DNA (n=4.0e8, sigma=16; markov4 stands in by family)": {
+            "n": 4.0e8, "pcWM_1core_s": 3.895, "pcWM_32core_s": 1.479, "psWM_1core_s": 4.293,
+            "psWM_32core_s": 0.904, "ddpcWM_32core_s": 0.691},
+        "1000G (n=88.2e8, sigma=4; markov4 stands in)": {
+            "n": 88.2e8, "pcWM_1core_s": 32.322, "pcWM_32core_s": 4.900, "psWM_1core_s": 30.908,
+            "psWM_32core_s": 6.969, "ddpcWM_32core_s": 2.429},
+        "WORDS (n=1.4e8, sigma=2245405; zipf20 stands in)": {
+            "n": 1.4e8, "pcWM_1core_s": 8.733, "pcWM_32core_s": 0.774, "psWM_1core_s": 13.394,
+            "psWM_32core_s": 3.007, "ddpcWM_32core_s": 4.308},
+    },
+}
+
+
+def paper_reference():
+    """Table 3 times with their throughput (n / t, symbols/s, one structure)."""
+    out = {"hardware": PAPER_TABLE3["hardware"], "what": PAPER_TABLE3["what"], "rows": {}}
+    for name, r in PAPER_TABLE3["rows"].items():
+        row = dict(r)
+        for k in list(r):
+            if k.endswith("_s"):
+                row[k[:-2] + "_symbols_per_s"] = round(r["n"] / r[k], 1)
+        out["rows"][name] = row
+    return out
+
+
+def pair_measure(B, d_text, n, b, L, steps, warmup, stream, dev, wt_s=None, wm_s=None):
+    """K pair builds (the WT and the WM of the text by wt_pair_build) timed
+    with HIP events; per-kernel durations from the events the library records
+    after every launch.  Returns (record, wt, wm)."""
+    import torch
+    if wt_s is None:
+        wt_s, wm_s = B.Structure(n, L, B.WT_TREE, device=dev), B.Structure(n, L, B.WT_MATRIX, device=dev)
+    pws = torch.empty(int(B.wt_pair_workspace_bytes(n, b, L)), dtype=torch.uint8, device=dev)
+    for _ in range(warmup):
+        B.pair_build(d_text, n, b, L, ws=pws, out=(wt_s, wm_s))
+    torch.cuda.synchronize()
+    probe = B.EventRecorder(512)
+    probe.pair_build(d_text, n, b, L, wt_s, wm_s, pws)
+    torch.cuda.synchronize()
+    rec = B.EventRecorder(probe.used * steps + 8)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        rec.pair_build(d_text, n, b, L, wt_s, wm_s, pws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    kt = rec.kernel_times(e0)
+    pk = {name: {"launches": len(v), "avg_ms": sum(v) / len(v)} for name, v in kt.items()}
+    for s in (wt_s, wm_s):
+        if s.status() != 0:
+            raise SystemExit(f"pair build status {s.status()}")
+    W = wt_s.view.words_per_level
+    G = -(-L // 8) if L else 1
+    # one group: the pair scatter writes both structures' levels; more
+    # groups: the WM's scatter launches, one group each
+    pbytes = n * b + 2 * L * W * 8 if L <= 8 else (n * b + L * W * 8) / G
+    pach = pbytes / (pk["scatter"]["avg_ms"] / 1e3) / 1e9
+    nb = W // 8
+    dir_bytes = L * (nb + 1) * 4 + 2 * L * ((n + 4095) // 4096 + 1) * 4
+    b_alg_build = 2 * n * b + L * W * 8 + dir_bytes
+    build_gbs = 2 * b_alg_build / (ms / 1e3) / 1e9
+    del pws
+    return ({"ms_per_step": ms, "value": 2 * n / (ms / 1e3), "kernels": pk, "b_alg_build": b_alg_build,
+             "build_alg_gbs": build_gbs,
+             "scatter": {"kernel": ("scatter (pair: WT and WM runs from one set of splits)" if L <= 8 else
+                                    "scatter (the WM's groups; the WT is gathered from the WM)"),
+                         "achieved": pach, "alg_bytes_per_launch": int(pbytes),
+                         "avg_launch_ms": pk["scatter"]["avg_ms"]}}, wt_s, wm_s)
+
+
+def config_line(B, name, steps, warmup, stream, dev, steady_args=None):
+    """One workload's pair step at its full size: time, symbols/s, the
+    scatter's roofline fraction and the whole step's fraction of the HBM peak
+    (algorithmic bytes of both builds), after an access check of sampled
+    positions against the text."""
+    import numpy as np
+    import torch
+
+    from paper_1702_07578_amd import inputs
+    t0 = time.time()
+    text, L = inputs.make(name)
+    n, b = text.size, text.dtype.itemsize
+    d_text = B.to_device(text, dev)
+    rec, wt_s, wm_s = pair_measure(B, d_text, n, b, L, steps, warmup, stream, dev)
+    pos = torch.from_numpy(inputs.u64(1 << 16, n, 99, 0).view(np.int64)).to(dev)
+    want = torch.from_numpy(text.astype(np.uint32).view(np.int32)).to(dev)[pos]
+    for s in (wt_s, wm_s):
+        if not torch.equal(s.access(pos), want):
+            raise SystemExit(f"{name}: access check failed")
+    sc = rec["scatter"]
+    out = {"workload": f"{name}: {WORKLOAD_TEXT.get(name, 'text')}, n={n} uint{8 * b} symbols, {L} levels",
+           "n": n, "sym_bytes": b, "lg_sigma": L, "steps": steps,
+           "ms_per_step": round(rec["ms_per_step"], 4), "symbols_per_s": round(rec["value"], 1),
+           "build_alg_gbs": round(rec["build_alg_gbs"], 1),
+           "build_alg_frac": round(rec["build_alg_gbs"] / HBM_PEAK_GBS, 4),
+           "scatter": {"kernel": sc["kernel"], "avg_launch_ms": round(sc["avg_launch_ms"], 4),
+                       "alg_bytes_per_launch": sc["alg_bytes_per_launch"], "achieved_gbs": round(sc["achieved"], 1),
+                       "frac": round(sc["achieved"] / HBM_PEAK_GBS, 4)},
+           "kernels": {k: {"avg_ms": round(v["avg_ms"], 4), "launches_per_step": v["launches"] // steps}
+                       for k, v in rec["kernels"].items()}}
+    if steady_args is not None:
+        out["steady_state"] = steady_state_small(steady_args, B, n, L, rec["b_alg_build"], log)
+    log(f"{name}: pair step {out['ms_per_step']} ms, scatter frac {out['scatter']['frac']}, "
+        f"step frac {out['build_alg_frac']} ({time.time() - t0:.1f}s)")
+    del wt_s, wm_s, d_text
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_batch(args):
     """Batched build of the 4096-text workload (WT and WM of every text) in
     one sequence of launches captured in a HIP graph, with autotuned knobs,
@@ -385,6 +543,11 @@ def main():
     ap.add_argument("--workload", default="markov96")
     ap.add_argument("--n", type=int, default=0, help="override the text length")
     ap.add_argument("--cpu-sample", type=int, default=1 << 26)
+    ap.add_argument("--cpu-sample-all", type=int, default=1 << 28,
+                    help="symbols of the all-cores oracle baseline")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other plain configurations after the headline")
+    ap.add_argument("--config-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile-log2", type=int, default=0)
     ap.add_argument("--group-bits", type=int, default=0)
@@ -509,49 +672,24 @@ def main():
                 "traffic": scatter_traffic(per_launch_bytes) if default_markov else None,
                 "alg_bytes_per_launch": int(per_launch_bytes), "avg_launch_ms": round(scat["avg_ms"], 4)}
     # both structures by the pair build (wt_pair_build): one pass when the
-    # levels fit one group, else the WM and the WT gathered from it; the
-    # same K steps, timed the same way
+    # levels fit one group, else the WM and the WT gathered from its
+    # intervals; the same K steps, timed the same way
     pair = None
     if L and B.wt_pair_workspace_bytes(n, b, L):
-        pws = torch.empty(int(B.wt_pair_workspace_bytes(n, b, L)), dtype=torch.uint8, device=dev)
-        wt_s, wm_s = structs[B.WT_TREE], structs[B.WT_MATRIX]
-        for _ in range(args.warmup):
-            B.pair_build(d_text, n, b, L, ws=pws, out=(wt_s, wm_s))
-        torch.cuda.synchronize()
-        probe2 = B.EventRecorder(512)
-        probe2.pair_build(d_text, n, b, L, wt_s, wm_s, pws)
-        torch.cuda.synchronize()
-        rec2 = B.EventRecorder(probe2.used * args.steps + 8)
-        torch.cuda.synchronize()
-        pe0 = torch.cuda.Event(enable_timing=True)
-        pe1 = torch.cuda.Event(enable_timing=True)
-        pe0.record(stream)
-        for _ in range(args.steps):
-            rec2.pair_build(d_text, n, b, L, wt_s, wm_s, pws)
-        pe1.record(stream)
-        torch.cuda.synchronize()
-        pair_ms = pe0.elapsed_time(pe1) / args.steps
-        pkt = rec2.kernel_times(pe0)
-        pk = {name: {"launches": len(v), "avg_ms": sum(v) / len(v)} for name, v in pkt.items()}
-        # one group: the pair scatter writes both structures' levels; more
-        # groups: the WM's scatter launches, one group each
-        pbytes = n * b + 2 * L * W * 8 if L <= 8 else (n * b + L * W * 8) / G
-        pach = pbytes / (pk["scatter"]["avg_ms"] / 1e3) / 1e9
-        pair = {"ms_per_step": pair_ms, "value": 2 * n / (pair_ms / 1e3), "kernels": pk,
-                "roofline": {"kernel": ("scatter (pair: WT and WM runs from one set of splits)" if L <= 8 else
-                                        "scatter (the WM's groups; the WT is gathered from the WM)"), "bound": "hbm",
+        prec, _, _ = pair_measure(B, d_text, n, b, L, args.steps, args.warmup, stream, dev,
+                                  structs[B.WT_TREE], structs[B.WT_MATRIX])
+        sc = prec["scatter"]
+        pair = {"ms_per_step": prec["ms_per_step"], "value": prec["value"], "kernels": prec["kernels"],
+                "roofline": {"kernel": sc["kernel"], "bound": "hbm",
                              "limiter": (valu_limiter(PAIR_COUNTERS, "7 levels of both structures",
-                                                      pk["scatter"]["avg_ms"]) if default_markov and L <= 8 else
+                                                      sc["avg_launch_ms"]) if default_markov and L <= 8 else
                                          "vector-instruction issue (counters taken on markov96 only)"),
-                             "achieved": round(pach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                             "frac": round(pach / HBM_PEAK_GBS, 4),
-                             "traffic": scatter_traffic(pbytes, PAIR_COUNTERS) if default_markov else None,
-                             "alg_bytes_per_launch": int(pbytes),
-                             "avg_launch_ms": round(pk["scatter"]["avg_ms"], 4)}}
-        for k, s in structs.items():
-            if s.status() != 0:
-                raise SystemExit(f"pair build status {s.status()} for kind {k}")
-        del pws
+                             "achieved": round(sc["achieved"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": round(sc["achieved"] / HBM_PEAK_GBS, 4),
+                             "traffic": (scatter_traffic(sc["alg_bytes_per_launch"], PAIR_COUNTERS)
+                                         if default_markov else None),
+                             "alg_bytes_per_launch": sc["alg_bytes_per_launch"],
+                             "avg_launch_ms": round(sc["avg_launch_ms"], 4)}}
 
     # whole-build roofline: B_alg = 2 n b + L W 8 + directories, per build
     nb = W // 8
@@ -673,9 +811,10 @@ def main():
     conv["posmap_queries_per_s"] = round(m / (pq_ms / 1e3), 1)
     del pm
 
-    cpu = None
+    cpu = cpu_all = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(text, L, min(args.cpu_sample, n))
+        cpu_all = cpu_baseline_all_cores(text, L, min(args.cpu_sample_all, n))
 
     log(f"step {ms_per_step:.3f} ms; kernels per step: " +
         ", ".join(f"{k} {v['total_ms_per_step']:.3f}ms" for k, v in sorted(kernels.items(), key=lambda x: -x[1]['total_ms_per_step'])))
@@ -716,6 +855,9 @@ def main():
                    "group_bits": args.group_bits or "auto"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "cpu_baseline_all_cores": cpu_all,
+        "host": host_info(),
+        "paper_reference": paper_reference(),
         "build_alg_gbs": round(build_gbs, 1),
         "build_alg_frac": round(build_gbs / HBM_PEAK_GBS, 4),
         "kernels": {k: {"avg_ms": round(v["avg_ms"], 4), "launches_per_step": v["launches"] // args.steps}
@@ -730,6 +872,15 @@ def main():
         # the small configuration: its step above is the isolated latency; this
         # is the steady-state rate of many such texts
         out["steady_state"] = steady_state_small(args, B, n, L, b_alg_build, log)
+    if default_markov and not args.no_configs:
+        # the other plain configurations at their full sizes, each by the
+        # pair step (the headline's structures and text are released first)
+        del structs, ws, d_text, pos, want, qpos, qsym
+        torch.cuda.empty_cache()
+        out["configs"] = {}
+        for name in ("uniform256", "markov4", "zipf20", "uniform16"):
+            steady = args if (name == "uniform256" and args.steady_texts) else None
+            out["configs"][name] = config_line(B, name, args.config_steps, args.warmup, stream, dev, steady)
     print(json.dumps(out), flush=True)
 
 
