@@ -134,22 +134,6 @@ __device__ __attribute__((always_inline)) inline void static_for(F &&f)
     }
 }
 
-// acc_lo/acc_hi of lane c := the 64-bit wave-uniform value B
-template <uint32_t c>
-__device__ inline void put_lane(uint32_t &acc_lo, uint32_t &acc_hi, uint64_t B)
-{
-    // B was just written by a vector compare; the compiler does not see into
-    // this block, so it does not insert the wait states a vector read of
-    // that SGPR pair needs: the s_nop gives them (the lane select is an
-    // inline constant)
-    asm volatile(
-        "s_nop 1\n\t"
-        "v_writelane_b32 %0, %2, %4\n\t"
-        "v_writelane_b32 %1, %3, %4"
-        : "+v"(acc_lo), "+v"(acc_hi)
-        : "s"((uint32_t)B), "s"((uint32_t)(B >> 32)), "n"(c));
-}
-
 // Base of the bit vectors group g writes: the output levels, or, for the
 // WT's later groups, its temporary WM levels; level a of the group starts
 // sm.lvw[a] words after it.  Word offsets fit 32 bits (L W < 2^31).
@@ -308,116 +292,145 @@ __device__ __attribute__((always_inline)) inline void run_end_words(const TextDe
     }
 }
 
-// One split (or, with SPLIT false, only the ballots) of the tile by bit
-// `bit`: the ballots are level a in the current order, and every symbol is
-// written to its place in the next order in LDS.  base1 is the tile's
-// number of zeros of that bit.  A tile shorter than kWaveTile is padded with
-// symbols whose bits are all one: they sort after every real symbol at every
-// level, so the real symbols keep their places and the padding fills the
-// end of every level's stream.
-template <typename E, bool REORDER, bool PAIR, uint32_t KB, bool SPLIT>
-__device__ __attribute__((always_inline)) inline void split_pass(uint32_t (&v)[kChunks], uint32_t a,
-                                                                 uint32_t bit, uint32_t base1,
-                                                                 WaveSmem<E, REORDER, PAIR, KB> &sm)
-{
-    const uint32_t lane = lane_id();
-    constexpr uint32_t e = sizeof(E);
-    // LDS address of the element buffer
-    const uint32_t ebase = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) E *)sm.elem;
-    uint32_t acc_lo = 0, acc_hi = 0;
-    base1 = __builtin_amdgcn_readfirstlane(base1);
-    // In chunk c a one goes to base1_c + (ones before the lane) and a zero to
-    // base0_c + (zeros before the lane), with base0_c + base1_c = base1 + 64 c:
-    // the two destinations of a lane add up to Q + 64 c (in bytes, times e).
-    // Both are taken 32 c e below their place, which the store's immediate
-    // offset adds back, so the zero's place is Q minus the one's.
-    const uint32_t Q = 2u * ebase + (base1 + lane) * e;
-    uint32_t t1 = ebase + base1 * e;  // the ones' base of chunk c, minus 32 c e
-    static_for<0, kChunks>([&](auto ci) {
-        constexpr uint32_t c = decltype(ci)::value;
-        const uint32_t x = v[c];
-        const bool one = (x & bit) != 0;
-        const uint64_t B = __ballot(one);
-        put_lane<c>(acc_lo, acc_hi, B);
-        if (SPLIT) {
-            uint32_t i1;
-            if (e == 1)
-                i1 = __builtin_amdgcn_mbcnt_hi((uint32_t)(B >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)B, t1));
-            else
-                i1 = t1 + __builtin_amdgcn_mbcnt_hi((uint32_t)(B >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)B, 0u)) * e;
-            const uint32_t i0 = Q - i1;
-            *(__attribute__((address_space(3))) E *)(uintptr_t)((one ? i1 : i0) + 32u * c * e) = (E)x;
-            t1 += __popcll(B) * e - 32u * e;
-            // opaque, so that it stays scalar and each chunk's ranks are not
-            // computed ahead of time (one register per chunk)
-            asm volatile("" : "+s"(t1));
-        }
-    });
-    if (lane < kChunks) sm.bits[a][lane] = ((uint64_t)acc_hi << 32) | acc_lo;
-}
-
-// The split of a byte tile, with every lane owning runs of 8 consecutive
+// The split of a tile, with every lane owning runs of 8 consecutive
 // positions: block b (of 4) of the tile order holds positions [512 b, 512 b +
-// 512), and lane l holds positions 512 b + 8 l + j, j = 0..7, as two 32-bit
-// words of four symbols.  Per block a lane then knows the bits of its own 8
-// positions: they form one byte of level a's word stream (byte 64 b + l), and
-// its ones before each of them come from a count of its own plus a wave scan
-// of the lanes' counts.  A symbol at position p with r ones before it in the
-// tile goes to base1 + r when its bit is one and to p - r when it is zero
-// (base1 = zeros of the bit in the tile).
+// 512), and lane l holds positions 512 b + 8 l + j, j = 0..7, as 8 symbols
+// in 2, 4 or 8 32-bit words (1-, 2- or 4-byte symbols).  Per block a lane
+// then knows the bits of its own 8 positions: they form one byte of level
+// a's word stream (byte 64 b + l), and its ones before each of them come from
+// a count of its own plus a wave scan of the lanes' counts.  A symbol at
+// position p with r ones before it in the tile goes to base1 + r when its bit
+// is one and to p - r when it is zero (base1 = zeros of the bit in the tile).
 
-// One symbol of a lane's run: VCC := its bit (byte j of the flag word f is
-// nonzero); the zero's place is K - X1 + i (K > X1 always; v_sad_u32 gives
-// |K - X1| + i); dest := bit ? X1 : that; X1 += bit.  VCC is the only scalar
-// register written; the sad sits between the compare and the first read of
-// VCC, which gives the one wait state a vector read of a vector-written
-// scalar register needs on this chip.
-template <uint32_t J, uint32_t I>
+// One symbol of a lane's run: VCC := its bit (part J of the flag word f is
+// nonzero: byte J for 1-byte symbols, half J for 2-byte ones, the word for
+// 4-byte ones); the zero's place is K - X1 + i (K > X1 always; v_sad_u32
+// gives |K - X1| + i); dest := bit ? X1 : that; X1 += bit.  VCC is the only
+// scalar register written; the sad sits between the compare and the first
+// read of VCC, which gives the one wait state a vector read of a
+// vector-written scalar register needs on this chip.
+template <uint32_t EB, uint32_t J, uint32_t I>
 __device__ __attribute__((always_inline)) inline uint32_t split_step(uint32_t f, uint32_t K, uint32_t &X1)
 {
     uint32_t d;
-    asm volatile(
-        "v_cmp_ne_u32_sdwa vcc, %[f], 0 src0_sel:BYTE_%c[j] src1_sel:DWORD\n\t"
-        "v_sad_u32 %[d], %[K], %[x], %[i]\n\t"
-        "v_cndmask_b32_e32 %[d], %[d], %[x], vcc\n\t"
-        "v_addc_co_u32_e32 %[x], vcc, 0, %[x], vcc"
-        : [d] "=&v"(d), [x] "+v"(X1)
-        : [f] "v"(f), [K] "v"(K), [j] "n"(J), [i] "n"(I)
-        : "vcc");
+    if constexpr (EB == 1)
+        asm volatile(
+            "v_cmp_ne_u32_sdwa vcc, %[f], 0 src0_sel:BYTE_%c[j] src1_sel:DWORD\n\t"
+            "v_sad_u32 %[d], %[K], %[x], %[i]\n\t"
+            "v_cndmask_b32_e32 %[d], %[d], %[x], vcc\n\t"
+            "v_addc_co_u32_e32 %[x], vcc, 0, %[x], vcc"
+            : [d] "=&v"(d), [x] "+v"(X1)
+            : [f] "v"(f), [K] "v"(K), [j] "n"(J), [i] "n"(I)
+            : "vcc");
+    else if constexpr (EB == 2)
+        asm volatile(
+            "v_cmp_ne_u32_sdwa vcc, %[f], 0 src0_sel:WORD_%c[j] src1_sel:DWORD\n\t"
+            "v_sad_u32 %[d], %[K], %[x], %[i]\n\t"
+            "v_cndmask_b32_e32 %[d], %[d], %[x], vcc\n\t"
+            "v_addc_co_u32_e32 %[x], vcc, 0, %[x], vcc"
+            : [d] "=&v"(d), [x] "+v"(X1)
+            : [f] "v"(f), [K] "v"(K), [j] "n"(J), [i] "n"(I)
+            : "vcc");
+    else
+        asm volatile(
+            "v_cmp_ne_u32_e32 vcc, 0, %[f]\n\t"
+            "v_sad_u32 %[d], %[K], %[x], %[i]\n\t"
+            "v_cndmask_b32_e32 %[d], %[d], %[x], vcc\n\t"
+            "v_addc_co_u32_e32 %[x], vcc, 0, %[x], vcc"
+            : [d] "=&v"(d), [x] "+v"(X1)
+            : [f] "v"(f), [K] "v"(K), [i] "n"(I)
+            : "vcc");
     return d;
 }
 
-// Ballots (SPLIT false) or split (SPLIT true) of a byte tile by bit bp of the
-// symbols; level a's word stream goes to sm.bits[a].  Returns nothing; the
-// tile's zero count of the bit comes from its own count, not from a table.
-template <typename E, bool REORDER, bool PAIR, uint32_t KB, bool SPLIT>
-__device__ __attribute__((always_inline)) inline void split_pass_bytes(uint32_t a, uint32_t bp,
-                                                                       WaveSmem<E, REORDER, PAIR, KB> &sm)
+// symbol j of a lane's run (j = 0..7) from its 32-bit words q, to the LDS
+// element at byte address dd
+template <typename E, uint32_t J>
+__device__ __attribute__((always_inline)) inline void put_elem(uint32_t dd, const uint32_t *q, const uint32_t *sq)
 {
-    static_assert(sizeof(E) == 1 && kWaveTile == 2048, "byte tiles of 4 blocks of 512");
     typedef __attribute__((address_space(3))) uint8_t lds_u8;
+    typedef __attribute__((address_space(3))) uint16_t lds_u16;
+    typedef __attribute__((address_space(3))) uint32_t lds_u32;
+    if constexpr (sizeof(E) == 1) {
+        // bytes 0 and 2 of a word directly, 1 and 3 from the word shifted by 8
+        constexpr uint32_t w = J / 4, by = J % 4;
+        const uint32_t x = (by & 1) ? sq[w] : q[w];
+        *(lds_u8 *)(uintptr_t)dd = (uint8_t)((by & 2) ? (x >> 16) : x);
+    } else if constexpr (sizeof(E) == 2) {
+        constexpr uint32_t w = J / 2;
+        *(lds_u16 *)(uintptr_t)dd = (uint16_t)((J & 1) ? (q[w] >> 16) : q[w]);
+    } else {
+        *(lds_u32 *)(uintptr_t)dd = q[J];
+    }
+}
+
+// Ballots (SPLIT false) or split (SPLIT true) of the tile by bit bp of the
+// symbols; level a's word stream goes to sm.bits[a].  The tile's zero count
+// of the bit comes from its own count, not from a table.
+template <typename E, bool REORDER, bool PAIR, uint32_t KB, bool SPLIT>
+__device__ __attribute__((always_inline)) inline void split_pass_lm(uint32_t a, uint32_t bp,
+                                                                    WaveSmem<E, REORDER, PAIR, KB> &sm)
+{
+    static_assert(kWaveTile == 2048, "tiles of 4 blocks of 512");
+    typedef __attribute__((address_space(3))) uint8_t lds_u8;
+    constexpr uint32_t EB = sizeof(E), NW = 2 * EB;  // 32-bit words of a lane's run
     const uint32_t lane = lane_id();
-    const uint32_t ebase = (uint32_t)(uintptr_t)(lds_u8 *)sm.elem;
-    uint32_t q[8];
+    const uint32_t ebase = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) E *)sm.elem;
+    uint32_t q[4][NW];
 #pragma unroll
     for (uint32_t b = 0; b < 4; b++) {
-        const uint2 u = *(const uint2 *)(sm.elem + 512 * b + 8 * lane);
-        q[2 * b] = u.x;
-        q[2 * b + 1] = u.y;
-    }
-    // bits past the symbol width (a byte text with more than 8 levels) are 0
-    const uint32_t mask = bp < 8 ? 0x01010101u << bp : 0u;
-    uint32_t f[8];
+        const uint32_t *src = (const uint32_t *)(sm.elem + 512 * b + 8 * lane);
+        if constexpr (NW == 2) {
+            const uint2 u = *(const uint2 *)src;
+            q[b][0] = u.x;
+            q[b][1] = u.y;
+        } else {
 #pragma unroll
-    for (uint32_t d = 0; d < 8; d++) f[d] = q[d] & mask;
-    // the lane's byte of the level word in each block, and its count
+            for (uint32_t i = 0; i < NW; i += 4) {
+                const uint4 u = *(const uint4 *)(src + i);
+                q[b][i] = u.x;
+                q[b][i + 1] = u.y;
+                q[b][i + 2] = u.z;
+                q[b][i + 3] = u.w;
+            }
+        }
+    }
+    // bits past the symbol width (a key above a narrow symbol) are 0
+    const uint32_t mask = bp >= 8 * EB ? 0u
+                          : EB == 1  ? 0x01010101u << bp
+                          : EB == 2  ? 0x00010001u << bp
+                                     : 1u << bp;
+    uint32_t f[4][NW];
+#pragma unroll
+    for (uint32_t b = 0; b < 4; b++)
+#pragma unroll
+        for (uint32_t w = 0; w < NW; w++) f[b][w] = q[b][w] & mask;
+    // the lane's byte of the level word in each block (bit j: symbol j), and
+    // its count
     uint32_t cnt[4];
     lds_u8 *lvl = (lds_u8 *)(uintptr_t)(uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint64_t *)sm.bits[a];
+    const uint32_t bsh = bp & 7;
 #pragma unroll
     for (uint32_t b = 0; b < 4; b++) {
-        const uint32_t w = __builtin_amdgcn_udot4(
-                               f[2 * b], 0x08040201u,
-                               __builtin_amdgcn_udot4(f[2 * b + 1], 0x80402010u, 0u, false), false) >> (bp & 7);
+        uint32_t w;
+        if constexpr (EB == 1) {
+            // flag bytes times 2^j, summed by two 4-way dot products
+            w = __builtin_amdgcn_udot4(f[b][0], 0x08040201u,
+                                       __builtin_amdgcn_udot4(f[b][1], 0x80402010u, 0u, false), false) >> bsh;
+        } else if constexpr (EB == 2) {
+            // the flag sits in byte 0 / 2 (bp < 8) or 1 / 3 (bp >= 8) of a word
+            const uint32_t up = bp >= 8 ? 8u : 0u;
+            uint32_t acc = 0;
+#pragma unroll
+            for (uint32_t wd = 0; wd < 4; wd++)
+                acc = __builtin_amdgcn_udot4(f[b][wd], ((1u << (2 * wd)) | (1u << (2 * wd + 1 + 16))) << up, acc,
+                                             false);
+            w = acc >> bsh;
+        } else {
+            w = 0;
+#pragma unroll
+            for (uint32_t j = 0; j < 8; j++) w |= (f[b][j] >> bp) << j;
+        }
         cnt[b] = __builtin_popcount(w);
         lvl[64 * b + lane] = (uint8_t)w;
     }
@@ -430,25 +443,30 @@ __device__ __attribute__((always_inline)) inline void split_pass_bytes(uint32_t 
     const uint32_t T0 = t01 & 0xFFFFu, T01 = T0 + (t01 >> 16), T012 = T01 + (t23 & 0xFFFFu);
     const uint32_t ones = T012 + (t23 >> 16);
     const uint32_t P1[4] = {e01 & 0xFFFFu, T0 + (e01 >> 16), T01 + (e23 & 0xFFFFu), T012 + (e23 >> 16)};
-    // base1 = zeros of the bit; ones go to ebase + base1 + (ones before)
-    const uint32_t X1base = ebase + (kWaveTile - ones);
+    // Ones go to base1 + (ones before), base1 = zeros of the bit.  The places
+    // are LDS byte addresses for 1-byte symbols; for wider ones they are
+    // symbol positions plus 16 (so that K - X1 >= 16 - 7 > 0), scaled to
+    // addresses at the store.
+    const uint32_t bias = EB == 1 ? ebase : 16u;
+    const uint32_t X1base = bias + kWaveTile - ones;
+    const uint32_t abase = ebase - 16u * EB;  // address of biased position 0 (EB > 1)
     // everything the lane reads is loaded; the writes below may overwrite it
     wave_sync();
 #pragma unroll
     for (uint32_t b = 0; b < 4; b++) {
         uint32_t X1 = X1base + P1[b];
-        const uint32_t K = X1base + ebase + 512 * b + 8 * lane;
-        const uint32_t fa = f[2 * b], fb = f[2 * b + 1], qa = q[2 * b], qb = q[2 * b + 1];
-        const uint32_t sa = qa >> 8, sb = qb >> 8;
-        uint32_t dd;
-        dd = split_step<0, 0>(fa, K, X1); *(lds_u8 *)(uintptr_t)dd = (uint8_t)qa;
-        dd = split_step<1, 1>(fa, K, X1); *(lds_u8 *)(uintptr_t)dd = (uint8_t)sa;
-        dd = split_step<2, 2>(fa, K, X1); *(lds_u8 *)(uintptr_t)dd = (uint8_t)(qa >> 16);
-        dd = split_step<3, 3>(fa, K, X1); *(lds_u8 *)(uintptr_t)dd = (uint8_t)(sa >> 16);
-        dd = split_step<0, 4>(fb, K, X1); *(lds_u8 *)(uintptr_t)dd = (uint8_t)qb;
-        dd = split_step<1, 5>(fb, K, X1); *(lds_u8 *)(uintptr_t)dd = (uint8_t)sb;
-        dd = split_step<2, 6>(fb, K, X1); *(lds_u8 *)(uintptr_t)dd = (uint8_t)(qb >> 16);
-        dd = split_step<3, 7>(fb, K, X1); *(lds_u8 *)(uintptr_t)dd = (uint8_t)(sb >> 16);
+        const uint32_t K = X1base + bias + 512 * b + 8 * lane;
+        uint32_t sq[2] = {0, 0};
+        if constexpr (EB == 1) {
+            sq[0] = q[b][0] >> 8;
+            sq[1] = q[b][1] >> 8;
+        }
+        static_for<0, 8>([&](auto jj) {
+            constexpr uint32_t j = decltype(jj)::value;
+            constexpr uint32_t fw = (j * EB) / 4, part = (EB == 4) ? 0u : (j % (4 / EB));
+            const uint32_t pos = split_step<EB, part, j>(f[b][fw], K, X1);
+            put_elem<E, j>(EB == 1 ? pos : abase + pos * EB, q[b], sq);
+        });
     }
 }
 
@@ -584,36 +602,19 @@ __device__ __attribute__((always_inline)) inline void wave_tile(const TextDesc &
             [&](uint32_t i, uint32_t x) { sm.loK[rev_bits(i, Kg)] = (uint16_t)x; });
     wave_sync();
 
-    // 4. split by one bit at a time; the ballots are the levels.  The zeros
-    //    of bit a in the tile: the start of the first key whose bit a is one,
-    //    in the order of level a + 1.
-    if constexpr (sizeof(E) == 1) {
-        for (uint32_t a = 0; a + 1 < Kg; a++) {
-            split_pass_bytes<E, REORDER, PAIR, KB, true>(a, shift + Kg - 1 - a, sm);
-            wave_sync();
-        }
-        split_pass_bytes<E, REORDER, PAIR, KB, REORDER>(Kg - 1, shift, sm);
+    // 4. split by one bit at a time; each pass's bits are level a in the
+    //    tile order of level a (Observation 2: after the splits by bits
+    //    0..a-1 the tile is ordered by its reversed a-bit key)
+    for (uint32_t a = 0; a + 1 < Kg; a++) {
+        split_pass_lm<E, REORDER, PAIR, KB, true>(a, shift + Kg - 1 - a, sm);
         wave_sync();
     }
-    uint32_t v[kChunks];
-    if constexpr (sizeof(E) != 1) {
-#pragma unroll
-        for (uint32_t c = 0; c < kChunks; c++) v[c] = sm.elem[c * 64 + lane];
-        wave_sync();
-        for (uint32_t a = 0; a + 1 < Kg; a++) {
-            split_pass<E, REORDER, PAIR, KB, true>(v, a, 1u << (shift + Kg - 1 - a), sm.lo[lvl_off(a + 1) + 1], sm);
-            wave_sync();
-#pragma unroll
-            for (uint32_t c = 0; c < kChunks; c++) v[c] = sm.elem[c * 64 + lane];
-            wave_sync();
-        }
-    }
+    split_pass_lm<E, REORDER, PAIR, KB, REORDER>(Kg - 1, shift, sm);
+    wave_sync();
     if (REORDER) {
-        // the last split orders the tile by its reversed Kg-bit key: each
+        // the last split ordered the tile by its reversed Kg-bit key: each
         // key's symbols, in text order, go to the key's place in the next
         // group's sequence (padding sorts last and is dropped)
-        if constexpr (sizeof(E) != 1) split_pass<E, REORDER, PAIR, KB, true>(v, Kg - 1, 1u << shift, sm.loK[1], sm);
-        wave_sync();
         E *gout = (E *)seq_out(d, g);
         for (uint32_t p = lane; p < len; p += 64) {
             const E x = sm.elem[p];
@@ -621,10 +622,8 @@ __device__ __attribute__((always_inline)) inline void wave_tile(const TextDesc &
             const uint32_t gi = sm.GK[k] + (p - sm.loK[k]);
             if (gi < d.n) gout[gi] = x;
         }
-    } else {
-        if constexpr (sizeof(E) != 1) split_pass<E, REORDER, PAIR, KB, false>(v, Kg - 1, 1u << shift, 0u, sm);
+        wave_sync();
     }
-    wave_sync();
 
     // 5. every level's runs to their interval starts (and, for the pair, to
     //    the WM's)
