@@ -471,15 +471,10 @@ def run_serve(args):
 
             if builds and rng.random() < 0.5:
                 target = int(rng.choice(builds[-64:]))
-                T, L = pool[reqs[target].text]
                 op = int(rng.integers(0, 3))
-                pos = rng.integers(0, T.size, size=qm, dtype=np.int64)
-                d_pos = torch.from_numpy(pos).to(dev)
-                if op == S.ACCESS:
-                    a = (d_pos,)
-                else:
-                    d_sym = torch.from_numpy(T[pos].astype(np.int32)).to(dev)
-                    a = (d_sym, d_pos) if op == S.RANK else (d_sym, torch.ones(qm, dtype=torch.int64, device=dev))
+                # positions drawn on the device at launch: j uniform, c = T[j],
+                # select's k = rank(c, j) + 1 (it answers j)
+                a = S.QuerySpec(m=qm, seed=(seed << 20) + rid)
                 reqs.append(S.Request(rid=rid, kind=S.QUERY, arrival=t, target=target, op=op, args=a))
             else:
                 reqs.append(S.Request(rid=rid, kind=S.BUILD, arrival=t, text=int(rng.integers(0, len(pool))),
@@ -489,7 +484,7 @@ def run_serve(args):
 
     def serve(reqs, slots, max_batch):
         ex = S.GpuExecutor(d_pool, slots)
-        srv = S.Server(ex, args.budget_gib << 30, slots=slots, max_batch=max_batch)
+        srv = S.Server(ex, int(args.budget_gib * (1 << 30)), slots=slots, max_batch=max_batch)
         w0 = time.perf_counter()
         done = srv.run(reqs)
         torch.cuda.synchronize()
@@ -500,9 +495,13 @@ def run_serve(args):
                 "query_p50_ms": round(st[S.QUERY]["p50_ms"], 3), "query_p99_ms": round(st[S.QUERY]["p99_ms"], 3),
                 "builds": st[S.BUILD]["count"], "query_batches": st[S.QUERY]["count"],
                 "failed": sum(r.status != 0 for r in done), "evictions": st["evictions"],
+                "refused": st["refused"], "lost_queries": st["lost_queries"],
                 "peak_gib": round(st["peak_bytes"] / 2 ** 30, 2), "wall_s": round(wall, 3),
                 "built_symbols_per_s": round(built / wall, 1)}
 
+    # warm-up: a short trace in both modes (first launches, allocator growth)
+    serve(trace(0.5, 3)[:200], args.slots, 64)
+    serve(trace(0.5, 3)[:200], 1, 1)
     results = {}
     for rho in (0.5, 0.9, 2.0):
         reqs = trace(rho, 11)
@@ -561,7 +560,9 @@ def main():
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--pool", type=int, default=64)
     ap.add_argument("--slots", type=int, default=4)
-    ap.add_argument("--budget-gib", type=int, default=64)
+    ap.add_argument("--budget-gib", type=float, default=4.0,
+                    help="HBM budget of the serving workload (below its working set, so that admission "
+                         "and eviction act)")
     args = ap.parse_args()
 
     if args.gpus != 1:

@@ -31,7 +31,11 @@ def _trace(texts, n_req, seed):
             op = int(rng.integers(0, 3))
             pos = rng.integers(0, T.size, size=m, dtype=np.int64)
             sym = T[pos].astype(np.int32)
-            if op == S.ACCESS:
+            if rng.random() < 0.5:
+                # inputs drawn on the device at launch (positions, symbols,
+                # and k = rank + 1 for select)
+                args = S.QuerySpec(m=m, seed=1000 + rid)
+            elif op == S.ACCESS:
                 args = (torch.from_numpy(pos).cuda(),)
             elif op == S.RANK:
                 args = (torch.from_numpy(sym).cuda(), torch.from_numpy(pos).cuda())
@@ -87,14 +91,26 @@ def test_mix_equals_alone(slots, budget):
         if r.kind != S.QUERY or by[r.rid].status != 0:
             continue
         s = alone[r.target]
+        inputs = by[r.rid].inputs
         if r.op == S.ACCESS:
-            want = s.access(*r.args)
+            want = s.access(*inputs)
         elif r.op == S.RANK:
-            want = s.rank(*r.args)
+            want = s.rank(*inputs)
         else:
-            want = s.select(*r.args)
+            want = s.select(*inputs)
         assert torch.equal(by[r.rid].result, want), f"query {r.rid}"
+        if isinstance(r.args, S.QuerySpec):
+            # drawn inputs: select answers the drawn positions, access the text
+            T, _ = texts[reqs[r.target].text]
+            if r.op == S.ACCESS:
+                assert np.array_equal(want.cpu().numpy().astype(np.int64),
+                                      T[inputs[0].cpu().numpy()].astype(np.int64))
+            elif r.op == S.SELECT:
+                ranks = s.rank(inputs[0], want)
+                assert torch.equal(ranks + 1, inputs[1]), f"query {r.rid}: rank(select(k)) != k - 1"
         answered += 1
     assert answered > 0
     if budget == 2 << 20:
         assert srv.evictions > 0
+    st = srv.stats()
+    assert st["refused"] + st["lost_queries"] == sum(r.status != 0 for r in done)

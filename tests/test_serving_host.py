@@ -20,8 +20,9 @@ class FakeExecutor:
     def footprint(self, r):
         return r.args["fp"]
 
-    def launch_builds(self, slot, reqs):
+    def launch_builds(self, slot, reqs, share=False):
         self.launches.append(("build", slot, [r.rid for r in reqs]))
+        self.shared = getattr(self, "shared", []) + [share]
         return {"reqs": reqs, "bytes": sum(r.footprint for r in reqs),
                 "end": self.clock.t + self.build_s}
 
@@ -148,3 +149,59 @@ def test_query_in_flight_pins_its_structure():
 def test_percentile_matches_numpy(q):
     xs = list(np.random.default_rng(3).exponential(1.0, size=101))
     assert S.percentile(xs, q) == pytest.approx(float(np.percentile(xs, q)))
+
+
+def _server_with(resident, budget, waiting=(), readers=()):
+    """A server in a given state: resident {rid: bytes} (oldest first),
+    waiting requests, and structures that queries in flight read."""
+    clock = Clock()
+    ex = FakeExecutor(clock)
+    srv = S.Server(ex, budget, slots=2)
+    for rid, nbytes in resident.items():
+        srv.resident[rid] = (("structure", rid), nbytes)
+        srv.resident_bytes += nbytes
+    srv.waiting.extend(waiting)
+    for rid in readers:
+        srv.readers[rid] += 1
+    return srv, ex
+
+
+def test_nothing_evicted_when_eviction_cannot_make_room():
+    # 100 of 150 held; 100 more needed; only 40 of the held bytes are
+    # movable (structure 1 is read by a query in flight): no eviction at all
+    srv, ex = _server_with({0: 40, 1: 60}, 150, readers=[1])
+    assert not srv._evict_for(100)
+    assert ex.freed == [] and srv.evictions == 0 and set(srv.resident) == {0, 1}
+    # once the query is done, both go (oldest first) and the request fits
+    srv.readers[1] -= 1
+    assert srv._evict_for(100)
+    assert ex.freed == [0, 1]
+
+
+def test_structures_that_waiting_queries_target_are_evicted_last():
+    # oldest is 0, but a waiting query targets it: 1 goes first
+    srv, ex = _server_with({0: 50, 1: 50, 2: 50}, 150, waiting=[query(9, 0.0, target=0)])
+    assert srv._evict_for(50)
+    assert ex.freed == [1]
+    assert srv._evict_for(150)
+    assert ex.freed == [1, 2, 0]
+
+
+def test_builds_share_the_chip_while_queries_run():
+    # a long query on structure 0 is in flight when build 2 launches: that
+    # build takes the capped grid; build 1, launched alone, does not
+    clock = Clock()
+    ex = FakeExecutor(clock, query_s=0.05)
+    srv = S.Server(ex, 10_000, slots=4)
+    reqs = [build(0, 0.0), build(1, 0.02), query(2, 0.04, target=0), build(3, 0.05)]
+    srv.run(reqs, clock=clock)
+    assert ex.shared == [False, False, True]
+
+
+def test_refusals_and_lost_queries_are_counted():
+    reqs = [build(0, 0.0, fp=80, keep=60), build(1, 0.02, fp=80, keep=60),
+            build(2, 0.04, fp=80, keep=60), query(3, 0.06, target=0),
+            build(4, 0.07, fp=1000)]
+    srv, ex, done, _ = run(reqs, budget=150)
+    st = srv.stats()
+    assert st["refused"] == 1 and st["lost_queries"] == 1 and st["evictions"] >= 1
