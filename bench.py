@@ -328,6 +328,13 @@ def run_batch(args):
         if not torch.equal(it[5].buf, s.buf):
             raise SystemExit(f"batched output differs from the plain build (n={it[1]}, L={it[3]})")
     value = 2 * total / (batch_ms / 1e3)
+    # algorithmic bytes of every structure of the batch: its text read twice,
+    # every level written once, the directories written once
+    alg = 0
+    for _, n, b, L, _, s in items:
+        W = s.view.words_per_level
+        alg += 2 * n * b + L * W * 8 + L * (W // 8 + 1) * 4 + 2 * L * ((n + 4095) // 4096 + 1) * 4
+    alg_gbs = alg / (batch_ms / 1e3) / 1e9
     out = {
         "metric": "batched WT+WM build throughput (symbols/s), one GPU",
         "value": round(value, 1), "unit": "symbols/s", "n_gpus": 1, "steps": args.steps,
@@ -338,6 +345,10 @@ def run_batch(args):
                                f"one graph-captured sequence of launches", "texts": len(texts),
                    "symbols": total, "tune": {"grid": tune.grid if tune else 0,
                                                "persist": tune.persist if tune else 0}},
+        "roofline": {"kernel": "the whole batched build (every kernel of the graph replay)", "bound": "hbm",
+                     "achieved": round(alg_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(alg_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "alg_bytes_per_launch": int(alg), "avg_launch_ms": round(batch_ms, 4)},
         "per_text_plain_ms": round(plain_ms, 3),
         "speedup_vs_per_text": round(plain_ms / batch_ms, 2),
         "autotune": [{"grid": g, "persist": p, "ms": ms, "status": st} for g, p, ms, st in table],

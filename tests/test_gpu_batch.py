@@ -221,3 +221,25 @@ def test_batch_pairs_share_one_pass(orc):
         for w, it in zip(want, items):
             for a, b in zip(w, _defined(it[5], it[1])):
                 assert np.array_equal(a, b)
+
+
+def test_every_autotune_candidate_reproduces_the_oracle(orc):
+    """The tuner keeps a candidate only when its outputs equal the default
+    configuration's; here every candidate of its search space is built on a
+    probe batch (mixed widths and alphabets, ranges of several tiles) and
+    compared with the oracle, and the tuner accepts all of them."""
+    import torch
+    from paper_1702_07578_amd import autotune
+    B = lib()
+    dev = torch.device("cuda:0")
+    texts = _batch(10, seed=13, lo_exp=8.0, hi_exp=17.0, extra=_edge_texts()[2:6])
+    items = _items(texts, dev)
+    tune, table = autotune.tune(items, reps=1)
+    assert all(st == "ok" for _, _, _, st in table), table
+    for g, p in autotune.CANDIDATES:
+        _garble(items)
+        print(f"[autotune] candidate grid={g} persist={p}", flush=True)
+        B.batch_build(items, tune=B.make_tune(grid=g, persist=p))
+        torch.cuda.synchronize()
+        for (T, L, kind), it in zip(texts, items):
+            assert_matches_oracle(orc, T, L, kind, it[5])
