@@ -263,6 +263,8 @@ __global__ __launch_bounds__(kBorderThreads) void k_borders(const TextDesc *__re
 
         // chunk prefix and totals of the finest keys
         uint32_t before = 0, all = 0;
+        // unrolled, so that several loads are in flight at once
+#pragma unroll 8
         for (uint32_t c2 = p; c2 < d.nchunks; c2 += P) {
             const uint32_t x = d.CS[(uint64_t)c2 * nk + k];
             all += x;

@@ -44,19 +44,33 @@ __global__ __launch_bounds__(256) void k_dir_count(const TextDesc *__restrict__ 
         if (l >= dir_levels(d, tmp)) continue;
         const uint64_t *bits = dir_bits(d, tmp, l);
         uint16_t *bc = d.dir_bc + (uint64_t)l * d.nb;
-        uint32_t sum = 0;
-        for (uint32_t r = 0; r < kDirChunk / 256; r++) {
-            const uint64_t j = (uint64_t)c * kDirChunk + r * 256 + threadIdx.x;
-            if (j < d.nb) {
-                const ulonglong2 *p = (const ulonglong2 *)(bits + j * 8);
-                uint32_t x = 0;
+        // The chunk's blocks as 16-byte units, four per block, lane-
+        // interleaved (consecutive lanes read consecutive units); the four
+        // lanes of a block add their counts across the quad.
+        constexpr uint32_t kUnits = kDirChunk * 4, kIters = kUnits / 256;
+        const ulonglong2 *p = (const ulonglong2 *)bits + (uint64_t)c * kUnits;
+        const uint64_t nblk = min((uint64_t)kDirChunk, d.nb - (uint64_t)c * kDirChunk);
+        const uint32_t units = (uint32_t)nblk * 4;
+        uint32_t x[kIters];
 #pragma unroll
-                for (int q = 0; q < 4; q++) {
-                    ulonglong2 v = p[q];
-                    x += __popcll(v.x) + __popcll(v.y);
-                }
-                bc[j] = (uint16_t)x;
-                sum += x;
+        for (uint32_t r = 0; r < kIters; r++) {
+            const uint32_t u = r * 256 + threadIdx.x;
+            x[r] = 0;
+            if (u < units) {
+                const ulonglong2 v = p[u];
+                x[r] = __popcll(v.x) + __popcll(v.y);
+            }
+        }
+        uint32_t sum = 0;
+#pragma unroll
+        for (uint32_t r = 0; r < kIters; r++) {
+            const uint32_t u = r * 256 + threadIdx.x;
+            uint32_t v = x[r];
+            v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+            v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+            if ((threadIdx.x & 3) == 0 && u < units) {
+                bc[(uint64_t)c * kDirChunk + (u >> 2)] = (uint16_t)v;
+                sum += v;
             }
         }
         // block sum

@@ -352,7 +352,7 @@ __device__ __attribute__((always_inline)) inline void put_elem(uint32_t dd, cons
     typedef __attribute__((address_space(3))) uint16_t lds_u16;
     typedef __attribute__((address_space(3))) uint32_t lds_u32;
     if constexpr (sizeof(E) == 1) {
-        // bytes 0 and 2 of a word directly, 1 and 3 from the word shifted by 8
+        // bytes 0 and 2 of a word directly, 1 and 3 from the word rotated by 8
         constexpr uint32_t w = J / 4, by = J % 4;
         const uint32_t x = (by & 1) ? sq[w] : q[w];
         *(lds_u8 *)(uintptr_t)dd = (uint8_t)((by & 2) ? (x >> 16) : x);
@@ -458,8 +458,12 @@ __device__ __attribute__((always_inline)) inline void split_pass_lm(uint32_t a, 
         const uint32_t K = X1base + bias + 512 * b + 8 * lane;
         uint32_t sq[2] = {0, 0};
         if constexpr (EB == 1) {
-            sq[0] = q[b][0] >> 8;
-            sq[1] = q[b][1] >> 8;
+            // bytes 1 and 3 of each word: the low byte and byte 2 of the word
+            // rotated by 8.  The rotation is opaque to the compiler, which
+            // would otherwise shift byte 3 down on its own instead of storing
+            // it from the upper half.
+            asm("v_alignbit_b32 %0, %1, %1, 8" : "=v"(sq[0]) : "v"(q[b][0]));
+            asm("v_alignbit_b32 %0, %1, %1, 8" : "=v"(sq[1]) : "v"(q[b][1]));
         }
         static_for<0, 8>([&](auto jj) {
             constexpr uint32_t j = decltype(jj)::value;
@@ -515,6 +519,9 @@ __device__ __attribute__((always_inline)) inline void wave_tile(const TextDesc &
     //    its counter (lane l adds to copy l mod 2^cb), so that the lanes of
     //    one atomic instruction do not all meet on a handful of words.
     const uint32_t cb = min(4u, KB - Kg), lane_copy = lane & ((1u << cb) - 1u);
+    // the lane's counter of key k: byte offset k << (cb + 2) from its copy 0
+    char *const cnt_lane = (char *)(cnt + lane_copy);
+    const uint32_t csh = cb + 2;
     for (uint32_t k = lane; k < (nk << cb); k += 64) cnt[k] = 0;
     wave_sync();
     if (!padded && vec) {
@@ -535,7 +542,7 @@ __device__ __attribute__((always_inline)) inline void wave_tile(const TextDesc &
             for (uint32_t j = 0; j < 4; j++)
 #pragma unroll
                 for (uint32_t s = 0; s < 4 / sizeof(E); s++)
-                    atomicAdd(&cnt[(__builtin_amdgcn_ubfe(w4[j], s * width + ks, kw) << cb) | lane_copy], 1u);
+                    atomicAdd((uint32_t *)(cnt_lane + (__builtin_amdgcn_ubfe(w4[j], s * width + ks, kw) << csh)), 1u);
         }
         if (kPrefetch<E>) {
             // the next tile of the range, when it is whole
