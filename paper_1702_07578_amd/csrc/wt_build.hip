@@ -108,7 +108,7 @@ __device__ void hist_range(const TextDesc &d, uint32_t g, uint32_t Kg, uint32_t 
     const uint32_t per_unit = 16 / sizeof(E);
     uint64_t done = 0;
     if (((uintptr_t)src & 15) == 0) {
-        const uint4 *u = (const uint4 *)src;
+        const gmem<uint4> *u = gp((const uint4 *)src);
         const uint64_t nu = len / per_unit;
         uint64_t i = tid;
         for (; i + 3 * kTileThreads < nu; i += 4 * kTileThreads) {
@@ -123,7 +123,7 @@ __device__ void hist_range(const TextDesc &d, uint32_t g, uint32_t Kg, uint32_t 
         done = nu * per_unit;
     }
     for (uint64_t i = done + tid; i < len; i += kTileThreads) {
-        const uint32_t e = src[i];
+        const uint32_t e = gp(src)[i];
         if (check && (e >> d.L) != 0) bad = true;
         atomicAdd(&hist[((e >> shift) & mask) << lc], 1u);
     }
@@ -141,7 +141,7 @@ __device__ void hist_range(const TextDesc &d, uint32_t g, uint32_t Kg, uint32_t 
             uint32_t t = 0;
 #pragma unroll
             for (uint32_t j = 0; j < (kTileWaves << lc); j++) t += sh[(j >> lc) * per_wave + (k << lc) + (j & 7)];
-            H[k] = t;
+            gp(H)[k] = t;
         }
         return;
     }
@@ -150,7 +150,7 @@ __device__ void hist_range(const TextDesc &d, uint32_t g, uint32_t Kg, uint32_t 
     uint32_t part = 0;
     for (uint32_t j = p; j < J; j += P) part += sh[(j >> lc) * per_wave + (k << lc) + (j & ((1u << lc) - 1u))];
     if (P == 1) {
-        H[k] = part;
+        gp(H)[k] = part;
         return;
     }
     __syncthreads();
@@ -160,7 +160,7 @@ __device__ void hist_range(const TextDesc &d, uint32_t g, uint32_t Kg, uint32_t 
         if (tid < half * nk) sh[tid] += sh[tid + half * nk];
         __syncthreads();
     }
-    if (tid < nk) H[tid] = sh[tid];
+    if (tid < nk) gp(H)[tid] = sh[tid];
 }
 
 __global__ __launch_bounds__(kTileThreads) void k_hist(const TextDesc *__restrict__ descs,
@@ -209,12 +209,12 @@ __global__ __launch_bounds__(256) void k_chunk_sum(const TextDesc *__restrict__ 
         const uint32_t r0 = c * d.CH, r1 = min(d.nranges, r0 + d.CH);
         uint32_t s = 0;
         if (p < P)
-            for (uint32_t r = r0 + p; r < r1; r += P) s += d.H[(uint64_t)r * nk + k];
+            for (uint32_t r = r0 + p; r < r1; r += P) s += gp(d.H)[(uint64_t)r * nk + k];
         part[threadIdx.x] = s;
         __syncthreads();
         if (p == 0) {
             for (uint32_t q = 1; q < P; q++) s += part[q * nk + k];
-            d.CS[(uint64_t)c * nk + k] = s;
+            gp(d.CS)[(uint64_t)c * nk + k] = s;
         }
         __syncthreads();
     }
@@ -266,7 +266,7 @@ __global__ __launch_bounds__(kBorderThreads) void k_borders(const TextDesc *__re
         // unrolled, so that several loads are in flight at once
 #pragma unroll 8
         for (uint32_t c2 = p; c2 < d.nchunks; c2 += P) {
-            const uint32_t x = d.CS[(uint64_t)c2 * nk + k];
+            const uint32_t x = gp(d.CS)[(uint64_t)c2 * nk + k];
             all += x;
             if (c2 < c) before += x;
         }
@@ -336,14 +336,14 @@ __global__ __launch_bounds__(kBorderThreads) void k_borders(const TextDesc *__re
         const uint32_t per = (d.CH + P - 1) / P;
         const uint32_t q0 = min(r1, r0 + p * per), q1 = min(r1, q0 + per);
         uint32_t s = 0;
-        for (uint32_t r = q0; r < q1; r++) s += d.H[(uint64_t)r * nk + k];
+        for (uint32_t r = q0; r < q1; r++) s += gp(d.H)[(uint64_t)r * nk + k];
         part[tid] = s;
         __syncthreads();
         uint32_t run = pre[k];
         for (uint32_t q = 0; q < p; q++) run += part[q * nk + k];
         for (uint32_t r = q0; r < q1; r++) {
-            const uint32_t x = d.H[(uint64_t)r * nk + k];
-            d.TP[(uint64_t)r * nk + k] = run;
+            const uint32_t x = gp(d.H)[(uint64_t)r * nk + k];
+            gp(d.TP)[(uint64_t)r * nk + k] = run;
             run += x;
         }
         __syncthreads();
@@ -354,7 +354,7 @@ __global__ __launch_bounds__(kBorderThreads) void k_borders(const TextDesc *__re
             uint32_t carry = 0;
             for (uint32_t base = 0; base < nk; base += 64) {
                 const uint32_t j = base + lane;
-                const uint32_t x = (j < nk) ? tp[j] : 0u;
+                const uint32_t x = (j < nk) ? gp(tp)[j] : 0u;
                 const uint32_t incl = wave_incl_scan(x);
                 if (j < nk) sw[j] = carry + incl - x;
                 carry += last_lane(incl);
@@ -368,10 +368,10 @@ __global__ __launch_bounds__(kBorderThreads) void k_borders(const TextDesc *__re
                 const uint32_t *kb = use_prefix_order(d, g, a, Kg) ? kbid : kbpi;
                 const uint32_t raw = sw[(kk + 1) << sh] - sw[kk << sh];
                 const uint32_t gs = raw + kb[e];
-                if ((gs & 63) != 0 && (gs >> 6) < d.W) level_ptr(d, g, a)[gs >> 6] = 0;
+                if ((gs & 63) != 0 && (gs >> 6) < d.W) gp(level_ptr(d, g, a))[gs >> 6] = 0;
                 if (d.pair && g == 0) {  // the pair's other structure, in its order
                     const uint32_t gs2 = raw + (d.kind == WT_MATRIX ? kbid : kbpi)[e];
-                    if ((gs2 & 63) != 0 && (gs2 >> 6) < d.W) d.bits2[(uint64_t)a * d.W + (gs2 >> 6)] = 0;
+                    if ((gs2 & 63) != 0 && (gs2 >> 6) < d.W) gp(d.bits2)[(uint64_t)a * d.W + (gs2 >> 6)] = 0;
                 }
             }
             if (r == 0) {

@@ -111,6 +111,32 @@ __device__ inline void *seq_out(const TextDesc &d, uint32_t g)
     return ((g + 1u) & 1u) ? d.seqA : d.seqB;
 }
 
+// Global-memory views of device pointers.  A pointer read from a descriptor
+// is generic to the compiler, which then emits flat instructions; a flat
+// access counts against the LDS wait counter as well as the vector-memory
+// one, so every later wait for an LDS result would also wait for it (a store
+// in flight would stall the next LDS read).  Accesses through these views
+// are global instructions.
+// (The host pass of this source sees the plain type: host code never
+// dereferences these pointers, and vector types have no address-space-
+// qualified copy there.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T>
+using gmem = __attribute__((address_space(1))) T;
+#else
+template <typename T>
+using gmem = T;
+#endif
+template <typename T>
+__device__ inline gmem<T> *gp(T *p)
+{
+    return (gmem<T> *)p;
+}
+__device__ inline void gatomic_or(uint64_t *p, uint64_t v)
+{
+    __hip_atomic_fetch_or(gp(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // number of set bits of mask in lanes below the calling lane
 __device__ inline uint32_t mbcnt64(uint64_t mask)
 {

@@ -48,7 +48,7 @@ __global__ __launch_bounds__(256) void k_dir_count(const TextDesc *__restrict__ 
         // interleaved (consecutive lanes read consecutive units); the four
         // lanes of a block add their counts across the quad.
         constexpr uint32_t kUnits = kDirChunk * 4, kIters = kUnits / 256;
-        const ulonglong2 *p = (const ulonglong2 *)bits + (uint64_t)c * kUnits;
+        const gmem<ulonglong2> *p = gp((const ulonglong2 *)bits) + (uint64_t)c * kUnits;
         const uint64_t nblk = min((uint64_t)kDirChunk, d.nb - (uint64_t)c * kDirChunk);
         const uint32_t units = (uint32_t)nblk * 4;
         uint32_t x[kIters];
@@ -69,7 +69,7 @@ __global__ __launch_bounds__(256) void k_dir_count(const TextDesc *__restrict__ 
             v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
             v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
             if ((threadIdx.x & 3) == 0 && u < units) {
-                bc[(uint64_t)c * kDirChunk + (u >> 2)] = (uint16_t)v;
+                gp(bc)[(uint64_t)c * kDirChunk + (u >> 2)] = (uint16_t)v;
                 sum += v;
             }
         }
@@ -80,7 +80,7 @@ __global__ __launch_bounds__(256) void k_dir_count(const TextDesc *__restrict__ 
         if (threadIdx.x == 0) {
             uint32_t s = 0;
             for (uint32_t i = 0; i < 256 / 64; i++) s += red[i];
-            d.dir_cs[(uint64_t)l * d.dir_chunks + c] = s;
+            gp(d.dir_cs)[(uint64_t)l * d.dir_chunks + c] = s;
         }
         __syncthreads();
     }
@@ -146,13 +146,13 @@ __global__ __launch_bounds__(256) void k_dir_write(const TextDesc *__restrict__ 
         uint32_t v[4], s = 0;
 #pragma unroll
         for (int r = 0; r < 4; r++) {
-            v[r] = (j0 + r < d.nb) ? bc[j0 + r] : 0u;
+            v[r] = (j0 + r < d.nb) ? gp(bc)[j0 + r] : 0u;
             s += v[r];
         }
         const uint32_t incl = wave_incl_scan(s);
         if (lane == 63) wsum[w] = incl;
         __syncthreads();
-        uint32_t pre = d.dir_cs[(uint64_t)l * d.dir_chunks + c];
+        uint32_t pre = gp(d.dir_cs)[(uint64_t)l * d.dir_chunks + c];
         for (uint32_t ww = 0; ww < w; ww++) pre += wsum[ww];
         pre += incl - s;
         uint32_t *s0 = d.sel0 + (uint64_t)l * d.sel_stride;
@@ -161,17 +161,17 @@ __global__ __launch_bounds__(256) void k_dir_write(const TextDesc *__restrict__ 
         for (int r = 0; r < 4; r++) {
             const uint64_t j = j0 + r;
             if (j < d.nb) {
-                rd[j] = pre;
+                gp(rd)[j] = pre;
                 if (!tmp) {
                     // the (4096 q + 1)-th one lies in block j iff pre < 4096 q + 1 <= pre + v
                     const uint64_t q1 = ((uint64_t)pre + WT_SEL_SPACING - 1) / WT_SEL_SPACING;
-                    if (q1 * WT_SEL_SPACING < (uint64_t)pre + v[r]) s1[q1] = (uint32_t)j;
+                    if (q1 * WT_SEL_SPACING < (uint64_t)pre + v[r]) gp(s1)[q1] = (uint32_t)j;
                     const uint64_t bstart = j * 512;
                     const uint64_t valid = bstart >= d.n ? 0 : min((uint64_t)512, d.n - bstart);
                     const uint64_t zpre = min(bstart, d.n) - pre;
                     const uint64_t zc = valid - v[r];
                     const uint64_t q0 = (zpre + WT_SEL_SPACING - 1) / WT_SEL_SPACING;
-                    if (q0 * WT_SEL_SPACING < zpre + zc) s0[q0] = (uint32_t)j;
+                    if (q0 * WT_SEL_SPACING < zpre + zc) gp(s0)[q0] = (uint32_t)j;
                 }
             }
             pre += v[r];

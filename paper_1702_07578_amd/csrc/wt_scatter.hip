@@ -156,7 +156,7 @@ __device__ inline void wave_range_start(const TextDesc &d, uint32_t g, uint32_t 
     const uint32_t nk = 1u << Kg;
     const uint32_t *TP = d.TP + (uint64_t)r * nk;
     uint32_t *T = sm.tmp32();
-    for (uint32_t k = lane; k < nk; k += 64) T[k] = TP[k];
+    for (uint32_t k = lane; k < nk; k += 64) T[k] = gp(TP)[k];
     wave_sync();
     for (uint32_t a = Kg; a-- > 0;) {
         const uint32_t *up = (a + 1 == Kg) ? T : sm.G + lvl_off(a + 1);
@@ -168,14 +168,14 @@ __device__ inline void wave_range_start(const TextDesc &d, uint32_t g, uint32_t 
         const uint32_t *kb = (use_prefix_order(d, g, a, Kg) ? d.KBid : d.KBpi) + lvl_off(a);
         for (uint32_t k = lane; k < (1u << a); k += 64) {
             const uint32_t raw = sm.G[lvl_off(a) + k];
-            sm.G[lvl_off(a) + k] = raw + kb[k];
+            sm.G[lvl_off(a) + k] = raw + gp(kb)[k];
             // the other structure: bit-reversed order for a WM, prefix order for a WT
-            if (PAIR) sm.G2[lvl_off(a) + k] = raw + (d.kind == WT_MATRIX ? d.KBid : d.KBpi)[lvl_off(a) + k];
+            if (PAIR) sm.G2[lvl_off(a) + k] = raw + gp(d.kind == WT_MATRIX ? d.KBid : d.KBpi)[lvl_off(a) + k];
         }
     }
     if (REORDER) {
         const uint32_t *kb = d.KBpi + lvl_off(Kg);
-        for (uint32_t k = lane; k < nk; k += 64) sm.GK[k] = T[k] + kb[k];
+        for (uint32_t k = lane; k < nk; k += 64) sm.GK[k] = T[k] + gp(kb)[k];
     }
     if (lane < Kg) sm.lvw[lane] = (group_level0(d, g) + lane) * (uint32_t)d.W;
     wave_sync();
@@ -245,7 +245,7 @@ __device__ __attribute__((always_inline)) inline void copy_full_words(const Text
     uint64_t *base = sd.base;
     for (uint32_t q = lane; q < total; q += 64) {
         const uint2 r = sm.co.rec[sm.co.kw[q]];
-        base[r.y + q] = stream64(&sm.bits[0][0], r.x + 64u * q);
+        gp(base)[r.y + q] = stream64(&sm.bits[0][0], r.x + 64u * q);
     }
     wave_sync();
 }
@@ -280,8 +280,8 @@ __device__ __attribute__((always_inline)) inline void run_end_words(const TextDe
         const bool lowok = off == 0 || pw == kPend;
         const bool head_full = off + cnt == 64;
         if (head && head_full && fw < W) {
-            if (lowok) base[sm.lvw[a] + fw] = hv;
-            else atomicOr((unsigned long long *)&base[sm.lvw[a] + fw], (unsigned long long)hv);
+            if (lowok) gp(base)[sm.lvw[a] + fw] = hv;
+            else gatomic_or(&base[sm.lvw[a] + fw], hv);
         }
         // the last word, when it is not the first and the run ends inside it
         const bool tail = lw != fw && (ge & 63) != 0;
@@ -484,7 +484,7 @@ struct TileUnits {
     uint4 q[kPerLane];
     __device__ void load(const E *tile)
     {
-        const uint4 *u = (const uint4 *)tile;
+        const gmem<uint4> *u = gp((const uint4 *)tile);
         const uint32_t lane = lane_id();
 #pragma unroll
         for (uint32_t i = 0; i < kPerLane; i++) q[i] = u[i * 64 + lane];
@@ -509,7 +509,7 @@ __device__ __attribute__((always_inline)) inline void wave_tile(const TextDesc &
     const bool padded = len < kWaveTile;
     const uint32_t shift = d.L - g * d.K - Kg;
     const uint32_t nk = 1u << Kg, kmask = nk - 1u;
-    const E *src = (const E *)seq_in(d, g) + start + lane;
+    const gmem<E> *src = gp((const E *)seq_in(d, g) + start + lane);
     uint32_t *cnt = sm.tmp32();
     uint16_t *P = sm.tmp16();
 
@@ -627,7 +627,7 @@ __device__ __attribute__((always_inline)) inline void wave_tile(const TextDesc &
             const E x = sm.elem[p];
             const uint32_t k = (x >> shift) & kmask;
             const uint32_t gi = sm.GK[k] + (p - sm.loK[k]);
-            if (gi < d.n) gout[gi] = x;
+            if (gi < d.n) gp(gout)[gi] = x;
         }
         wave_sync();
     }
@@ -675,14 +675,12 @@ __device__ void wave_range(const TextDesc &d, uint32_t g, uint32_t Kg, uint32_t 
         if (sm.pend[e] != kNoPend) {
             const uint32_t wd = sm.G[e] >> 6;
             if (wd < (uint32_t)d.W)
-                atomicOr((unsigned long long *)&group_base(d, g)[sm.lvw[level_of(e)] + wd],
-                         (unsigned long long)sm.pend_v[e]);
+                gatomic_or(&group_base(d, g)[sm.lvw[level_of(e)] + wd], sm.pend_v[e]);
         }
         if (PAIR && sm.pend2[e] != kNoPend) {
             const uint32_t wd = sm.G2[e] >> 6;
             if (wd < (uint32_t)d.W)
-                atomicOr((unsigned long long *)&d.bits2[sm.lvw[level_of(e)] + wd],
-                         (unsigned long long)sm.pend_v2[e]);
+                gatomic_or(&d.bits2[sm.lvw[level_of(e)] + wd], sm.pend_v2[e]);
         }
     }
     wave_sync();
