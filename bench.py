@@ -60,24 +60,47 @@ def scatter_traffic(per_launch_alg_bytes, path=COUNTERS):
     return c.get("bytes_per_launch")
 
 
-def valu_limiter(path, what, avg_ms):
-    """The scatter's limiter from the committed instruction counters: VALU
-    instructions per 64 symbols and, at this run's launch time, the share of
-    the chip's VALU issue rate they take (1024 SIMDs at 2.4 GHz, one wave64
-    instruction per SIMD every 4 cycles).  Counters taken on another version
-    of the kernel source are not used."""
-    if os.path.exists(path):
-        c = json.load(open(path))
-        src = hashlib.sha256(open(SCATTER_SRC, "rb").read()).hexdigest()
-        if c.get("source_sha256") == src and "sq" in c:
-            sq = c["sq"]
-            valu = sq["per_dispatch_median"]["SQ_INSTS_VALU"]
-            issue = 1024 * 2.4e9 / 4
-            frac = valu / (avg_ms / 1e3 * issue)
-            return (f"vector-instruction issue: about {sq['valu_per_64_symbols']:.0f} VALU instructions per 64 "
-                    f"symbols for {what} (rocprofv3 SQ_INSTS_VALU), about {100 * frac:.0f}% of the chip's VALU "
-                    f"issue rate (1024 SIMDs x 2.4 GHz / 4 cycles per wave64 instruction)")
-    return "vector-instruction issue (instruction counters not taken on this kernel source)"
+# the chip's vector-instruction issue rate: 256 CUs x 4 SIMDs, one wave64
+# VALU instruction per SIMD every 4 cycles at 2.4 GHz
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
+
+
+def src_sha():
+    return hashlib.sha256(open(SCATTER_SRC, "rb").read()).hexdigest()
+
+
+def alu_issue(workload, scatter_ms_per_step, path=None):
+    """The pair step's scatter against the chip's VALU issue rate, from the
+    committed instruction counters of that workload (rocprofv3 SQ_INSTS_VALU
+    summed over one pair step's scatter dispatches), or None when there are
+    none or the kernel source changed since they were taken."""
+    path = path or os.path.join(ROOT, "profiles", f"scatter_issue_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    c = json.load(open(path))
+    if c.get("source_sha256") != src_sha():
+        return None
+    ach = c["valu_per_step"] / (scatter_ms_per_step / 1e3)
+    return {"achieved": round(ach / 1e9, 1), "peak": round(VALU_ISSUE_PEAK / 1e9, 1),
+            "unit": "G wave64 VALU instructions/s", "frac": round(ach / VALU_ISSUE_PEAK, 4),
+            "valu_per_64_symbols": c["valu_per_64_symbols"], "lds_per_64_symbols": c["lds_per_64_symbols"],
+            "counters": os.path.relpath(path, ROOT)}
+
+
+def single_alu_issue(avg_ms, path=COUNTERS):
+    """The single build's scatter against the VALU issue rate, from the
+    committed counters of its markov96 launches (same source only)."""
+    if not os.path.exists(path):
+        return None
+    c = json.load(open(path))
+    if c.get("source_sha256") != src_sha() or "sq" not in c:
+        return None
+    sq = c["sq"]
+    ach = sq["per_dispatch_median"]["SQ_INSTS_VALU"] / (avg_ms / 1e3)
+    return {"achieved": round(ach / 1e9, 1), "peak": round(VALU_ISSUE_PEAK / 1e9, 1),
+            "unit": "G wave64 VALU instructions/s", "frac": round(ach / VALU_ISSUE_PEAK, 4),
+            "valu_per_64_symbols": sq["valu_per_64_symbols"], "lds_per_64_symbols": sq["lds_per_64_symbols"],
+            "counters": os.path.relpath(path, ROOT)}
 
 
 def cpu_baseline(text, L, sample_n):
@@ -209,7 +232,20 @@ def pair_measure(B, d_text, n, b, L, steps, warmup, stream, dev, wt_s=None, wm_s
              "scatter": {"kernel": ("scatter (pair: WT and WM runs from one set of splits)" if L <= 8 else
                                     "scatter (the WM's groups; the WT is gathered from the WM)"),
                          "achieved": pach, "alg_bytes_per_launch": int(pbytes),
-                         "avg_launch_ms": pk["scatter"]["avg_ms"]}}, wt_s, wm_s)
+                         "avg_launch_ms": pk["scatter"]["avg_ms"],
+                         "ms_per_step": pk["scatter"]["avg_ms"] * pk["scatter"]["launches"] / steps}},
+            wt_s, wm_s)
+
+
+def bound_fields(workload, scatter_ms_per_step):
+    """What bounds the scatter: vector-instruction issue when the committed
+    counters of this kernel source measure it (achieved against the issue
+    rate under "alu"), else not measured.  The roofline's own figures stay
+    algorithmic bytes against the HBM peak."""
+    alu = alu_issue(workload, scatter_ms_per_step)
+    if alu is None:
+        return {"bound": "hbm", "limiter": "not measured on this kernel source (no matching instruction counters)"}
+    return {"bound": "alu", "alu": alu}
 
 
 def config_line(B, name, steps, warmup, stream, dev, steady_args=None):
@@ -239,7 +275,8 @@ def config_line(B, name, steps, warmup, stream, dev, steady_args=None):
            "build_alg_frac": round(rec["build_alg_gbs"] / HBM_PEAK_GBS, 4),
            "scatter": {"kernel": sc["kernel"], "avg_launch_ms": round(sc["avg_launch_ms"], 4),
                        "alg_bytes_per_launch": sc["alg_bytes_per_launch"], "achieved_gbs": round(sc["achieved"], 1),
-                       "frac": round(sc["achieved"] / HBM_PEAK_GBS, 4)},
+                       "frac": round(sc["achieved"] / HBM_PEAK_GBS, 4),
+                       **bound_fields(name, sc["ms_per_step"])},
            "kernels": {k: {"avg_ms": round(v["avg_ms"], 4), "launches_per_step": v["launches"] // steps}
                        for k, v in rec["kernels"].items()}}
     if steady_args is not None:
@@ -559,6 +596,9 @@ def main():
                     help="skip the other plain configurations after the headline")
     ap.add_argument("--config-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--step-only", action="store_true",
+                    help="only the pair step (warm-up, one probe step, then the timed steps): the "
+                         "launches a counter run profiles")
     ap.add_argument("--tile-log2", type=int, default=0)
     ap.add_argument("--group-bits", type=int, default=0)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -611,6 +651,14 @@ def main():
         del x, y
         log("copy calibration: 3 x bitwise_not over 2^28 int32 (1 GiB read + 1 GiB write each)")
     d_text = B.to_device(text, dev)
+    if args.step_only:
+        # warm-up steps, one probe step and the timed steps of the pair build,
+        # nothing else: (warmup + 1 + steps) pair builds in all
+        rec, _, _ = pair_measure(B, d_text, n, b, L, args.steps, args.warmup, stream, dev)
+        print(json.dumps({"workload": args.workload, "n": n, "sym_bytes": b, "lg_sigma": L,
+                          "pair_builds": args.warmup + 1 + args.steps, "ms_per_step": round(rec["ms_per_step"], 4),
+                          "scatter_ms_per_step": round(rec["scatter"]["ms_per_step"], 4)}), flush=True)
+        return
     tune = B.make_tune(tile_log2=args.tile_log2, group_bits=args.group_bits)
     structs = {k: B.Structure(n, L, k, device=dev) for k in (B.WT_TREE, B.WT_MATRIX)}
     ws_bytes = max(B.workspace_bytes(n, b, L, k, tune) for k in structs)
@@ -676,9 +724,10 @@ def main():
     per_launch_bytes = (n * b + L * W * 8) / max(1, G)
     achieved = per_launch_bytes / (scat["avg_ms"] / 1e3) / 1e9
     default_markov = args.workload == "markov96" and not args.n
-    roofline = {"kernel": "scatter", "bound": "hbm",
-                "limiter": (valu_limiter(COUNTERS, "7 levels", scat["avg_ms"]) if default_markov else
-                            "vector-instruction issue (counters taken on markov96 only)"),
+    single_alu = single_alu_issue(scat["avg_ms"]) if default_markov else None
+    roofline = {"kernel": "scatter",
+                **({"bound": "alu", "alu": single_alu} if single_alu else
+                   {"bound": "hbm", "limiter": "not measured on this workload or kernel source"}),
                 "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": scatter_traffic(per_launch_bytes) if default_markov else None,
@@ -692,10 +741,9 @@ def main():
                                   structs[B.WT_TREE], structs[B.WT_MATRIX])
         sc = prec["scatter"]
         pair = {"ms_per_step": prec["ms_per_step"], "value": prec["value"], "kernels": prec["kernels"],
-                "roofline": {"kernel": sc["kernel"], "bound": "hbm",
-                             "limiter": (valu_limiter(PAIR_COUNTERS, "7 levels of both structures",
-                                                      sc["avg_launch_ms"]) if default_markov and L <= 8 else
-                                         "vector-instruction issue (counters taken on markov96 only)"),
+                "roofline": {"kernel": sc["kernel"],
+                             **(bound_fields(args.workload, sc["ms_per_step"]) if not args.n else
+                                {"bound": "hbm", "limiter": "not measured at this text length"}),
                              "achieved": round(sc["achieved"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": round(sc["achieved"] / HBM_PEAK_GBS, 4),
                              "traffic": (scatter_traffic(sc["alg_bytes_per_launch"], PAIR_COUNTERS)

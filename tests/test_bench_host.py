@@ -1,6 +1,7 @@
-"""Host-side logic of bench.py: the roofline's traffic and limiter come from the
-committed counter files only when those were taken on the current scatter
-source (checked by hash); and the benchmark refuses more than one GPU."""
+"""Host-side logic of bench.py: the roofline's traffic and its VALU-issue
+figures come from the committed counter files only when those were taken on
+the current scatter source (checked by hash); and the benchmark refuses more
+than one GPU."""
 import hashlib
 import json
 import os
@@ -20,7 +21,9 @@ def _counters(tmp_path, src_text, sha=None, valu=1.5e9, per64=89.4, bytes_per_la
     src.write_text(src_text)
     c = {"source_sha256": sha if sha is not None else hashlib.sha256(src.read_bytes()).hexdigest(),
          "bytes_per_launch": bytes_per_launch,
-         "sq": {"per_dispatch_median": {"SQ_INSTS_VALU": valu}, "valu_per_64_symbols": per64}}
+         "valu_per_step": valu, "valu_per_64_symbols": per64, "lds_per_64_symbols": 13.0,
+         "sq": {"per_dispatch_median": {"SQ_INSTS_VALU": valu}, "valu_per_64_symbols": per64,
+                "lds_per_64_symbols": 13.0}}
     path = tmp_path / "counters.json"
     path.write_text(json.dumps(c))
     return str(src), str(path)
@@ -31,17 +34,17 @@ def test_counters_used_when_source_matches(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "SCATTER_SRC", src)
     assert bench.scatter_traffic(1, path) == 5_000_000_000
     # 1.5e9 VALU instructions in 2.5 ms against 1024 SIMDs x 2.4 GHz / 4
-    lim = bench.valu_limiter(path, "7 levels", 2.5)
     frac = 1.5e9 / (2.5e-3 * 1024 * 2.4e9 / 4)
-    assert f"about {round(100 * frac)}%" in lim
-    assert "about 89 VALU instructions per 64 symbols for 7 levels" in lim
+    for alu in (bench.alu_issue("w", 2.5, path), bench.single_alu_issue(2.5, path)):
+        assert alu["frac"] == round(frac, 4)
+        assert alu["peak"] == 614.4 and alu["valu_per_64_symbols"] == 89.4
 
 
 def test_counters_ignored_when_source_changed(tmp_path, monkeypatch):
     src, path = _counters(tmp_path, "kernel source A", sha="0" * 64)
     monkeypatch.setattr(bench, "SCATTER_SRC", src)
     assert bench.scatter_traffic(1, path) is None
-    assert "not taken" in bench.valu_limiter(path, "7 levels", 2.5)
+    assert bench.alu_issue("w", 2.5, path) is None and bench.single_alu_issue(2.5, path) is None
 
 
 def test_counters_missing(tmp_path, monkeypatch):
@@ -49,7 +52,9 @@ def test_counters_missing(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "SCATTER_SRC", src)
     missing = str(tmp_path / "none.json")
     assert bench.scatter_traffic(1, missing) is None
-    assert "not taken" in bench.valu_limiter(missing, "7 levels", 2.5)
+    assert bench.alu_issue("w", 2.5, missing) is None and bench.single_alu_issue(2.5, missing) is None
+    # the roofline then names no limiter it has not measured
+    assert bench.bound_fields("no such workload", 2.5)["bound"] == "hbm"
 
 
 def test_committed_counters_are_well_formed():
