@@ -329,6 +329,9 @@ static int convert_one(const wt_levels *src, wt_levels *dst, void *d_ws, size_t 
                        const wtg::LaunchCtx &ctx);
 namespace wtg {
 
+// workspace head of a one-pass pair build: the two descriptors
+static size_t pair_head_bytes() { return align_up(2 * sizeof(TextDesc), 256); }
+
 // Both structures of one text.  With one group, the WT's build also writes
 // the WM from the same tile splits (the two differ only in where each run of
 // a level goes: prefix order or bit-reversed order, Section 5.1); with more
@@ -354,11 +357,11 @@ static int pair_one(const void *d_text, uint64_t n, uint32_t b, uint32_t L, wt_l
         // the build's workspace is free again once the stream passes it
         return ::convert_one(wm, wt, d_ws, ws_bytes, ctx);
     }
-    const uint64_t dsz = align_up(sizeof(TextDesc), 256);
-    if (ws_bytes < p.bytes + 2 * dsz + 256) return WT_ENOSPACE;
+    if (ws_bytes < p.bytes + pair_head_bytes() + 256) return WT_ENOSPACE;
     uint8_t *base = (uint8_t *)align_up((uintptr_t)d_ws, 256);
-    TextDesc *d_desc = (TextDesc *)base, *d_desc2 = (TextDesc *)(base + dsz);
-    bind_ws(p, base + 2 * dsz);
+    // the two descriptors next to each other (the WT's, then the WM's)
+    TextDesc *d_desc = (TextDesc *)base, *d_desc2 = d_desc + 1;
+    bind_ws(p, base + pair_head_bytes());
     p.d.text = d_text;
     bind_out(p.d, *wt);
     TextDesc d2 = p.d;  // the WM, for its directories
@@ -371,12 +374,13 @@ static int pair_one(const void *d_text, uint64_t n, uint32_t b, uint32_t L, wt_l
     std::vector<TextDesc> ds{p.d};
     Sched s;
     if ((rc = schedule(ds, s)) != WT_OK) return rc;
-    if (launch_init(d2, d_desc2, ctx) != hipSuccess) return WT_EHIP;
-    if (launch_init(p.d, d_desc, ctx) != hipSuccess) return WT_EHIP;
+    if (launch_init_pair(p.d, d2, d_desc, ctx) != hipSuccess) return WT_EHIP;
     DevBases bb;
     bb.walk.assign(s.walk_items.size(), nullptr);
     const uint32_t cap = tune ? tune->persist : 0;
     if (run_build(d_desc, s, bb, cap, ctx) != hipSuccess) return WT_EHIP;
+    // the WM's directories after the WT's: the two share the workspace's
+    // block-count arrays
     if (launch_dirs(d_desc2, nullptr, 1, s.dir_items, s.max_levels, false, cap, ctx) != hipSuccess)
         return WT_EHIP;
     return WT_OK;
@@ -386,7 +390,7 @@ static size_t pair_ws_bytes(uint64_t n, uint32_t b, uint32_t L, const wt_tune *t
 {
     WsPlan p;
     if (plan_text(n, b, L, WT_TREE, tune, p) != WT_OK) return 0;
-    if (p.d.G == 1 && L > 0) return p.bytes + 2 * align_up(sizeof(TextDesc), 256) + 256;
+    if (p.d.G == 1 && L > 0) return p.bytes + pair_head_bytes() + 256;
     WsPlan q;
     if (plan_text(n, b, L, WT_MATRIX, tune, q) != WT_OK) return 0;
     size_t need = q.bytes + align_up(sizeof(TextDesc), 256) + 256;

@@ -37,6 +37,23 @@ __global__ void k_init(TextDesc d, TextDesc *dst)
     }
 }
 
+// pair (WT and WM of one text from one pass): both descriptors in one
+// launch, stored next to each other (the WM's serves its directories), and
+// both status words and Z cleared
+__global__ void k_init_pair(TextDesc d, TextDesc d2, TextDesc *dst)
+{
+    if (threadIdx.x == 0) {
+        dst[0] = d;
+        dst[1] = d2;
+        *d.status = WT_OK;
+        *d2.status = WT_OK;
+    }
+    for (uint32_t l = threadIdx.x; l < d.L; l += blockDim.x) {
+        d.zeros[l] = 0;
+        d2.zeros[l] = 0;
+    }
+}
+
 // batch: clear the status word and Z of every text
 __global__ void k_init_batch(const TextDesc *__restrict__ descs, uint32_t nd)
 {
@@ -564,6 +581,13 @@ static inline uint32_t grid_for(uint32_t nitems, uint32_t cap)
 hipError_t launch_init(const TextDesc &d, TextDesc *d_dst, const LaunchCtx &ctx)
 {
     hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, ctx.stream, d, d_dst);
+    after(ctx, KID_INIT);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_pair(const TextDesc &d, const TextDesc &d2, TextDesc *d_dst, const LaunchCtx &ctx)
+{
+    hipLaunchKernelGGL(k_init_pair, dim3(1), dim3(64), 0, ctx.stream, d, d2, d_dst);
     after(ctx, KID_INIT);
     return hipGetLastError();
 }

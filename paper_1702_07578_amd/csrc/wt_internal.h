@@ -164,6 +164,7 @@ struct GroupLaunch {
 };
 
 hipError_t launch_init(const TextDesc &d, TextDesc *d_dst, const LaunchCtx &ctx);
+hipError_t launch_init_pair(const TextDesc &d, const TextDesc &d2, TextDesc *d_dst, const LaunchCtx &ctx);
 hipError_t launch_init_batch(const TextDesc *d_descs, uint32_t nd, const LaunchCtx &ctx);
 hipError_t launch_group(const TextDesc *d_descs, const GroupLaunch &gl, const LaunchCtx &ctx);
 hipError_t launch_scatter(const TextDesc *d_descs, const GroupLaunch &gl, const LaunchCtx &ctx);
