@@ -302,44 +302,24 @@ __device__ __attribute__((always_inline)) inline void run_end_words(const TextDe
 // position p with r ones before it in the tile goes to base1 + r when its bit
 // is one and to p - r when it is zero (base1 = zeros of the bit in the tile).
 
-// One symbol of a lane's run: VCC := its bit (part J of the flag word f is
-// nonzero: byte J for 1-byte symbols, half J for 2-byte ones, the word for
-// 4-byte ones); the zero's place is K - X1 + i (K > X1 always; v_sad_u32
-// gives |K - X1| + i); dest := bit ? X1 : that; X1 += bit.  VCC is the only
-// scalar register written; the sad sits between the compare and the first
-// read of VCC, which gives the one wait state a vector read of a
-// vector-written scalar register needs on this chip.
-template <uint32_t EB, uint32_t J, uint32_t I>
+// One symbol of a lane's run: VCC := its bit (byte J of the flag word f is
+// nonzero); the zero's place is K - X1 + i (K > X1 always; v_sad_u32 gives
+// |K - X1| + i); dest := bit ? X1 : that; X1 += bit.  VCC is the only scalar
+// register written; the sad sits between the compare and the first read of
+// VCC, which gives the one wait state a vector read of a vector-written
+// scalar register needs on this chip.
+template <uint32_t J, uint32_t I>
 __device__ __attribute__((always_inline)) inline uint32_t split_step(uint32_t f, uint32_t K, uint32_t &X1)
 {
     uint32_t d;
-    if constexpr (EB == 1)
-        asm volatile(
-            "v_cmp_ne_u32_sdwa vcc, %[f], 0 src0_sel:BYTE_%c[j] src1_sel:DWORD\n\t"
-            "v_sad_u32 %[d], %[K], %[x], %[i]\n\t"
-            "v_cndmask_b32_e32 %[d], %[d], %[x], vcc\n\t"
-            "v_addc_co_u32_e32 %[x], vcc, 0, %[x], vcc"
-            : [d] "=&v"(d), [x] "+v"(X1)
-            : [f] "v"(f), [K] "v"(K), [j] "n"(J), [i] "n"(I)
-            : "vcc");
-    else if constexpr (EB == 2)
-        asm volatile(
-            "v_cmp_ne_u32_sdwa vcc, %[f], 0 src0_sel:WORD_%c[j] src1_sel:DWORD\n\t"
-            "v_sad_u32 %[d], %[K], %[x], %[i]\n\t"
-            "v_cndmask_b32_e32 %[d], %[d], %[x], vcc\n\t"
-            "v_addc_co_u32_e32 %[x], vcc, 0, %[x], vcc"
-            : [d] "=&v"(d), [x] "+v"(X1)
-            : [f] "v"(f), [K] "v"(K), [j] "n"(J), [i] "n"(I)
-            : "vcc");
-    else
-        asm volatile(
-            "v_cmp_ne_u32_e32 vcc, 0, %[f]\n\t"
-            "v_sad_u32 %[d], %[K], %[x], %[i]\n\t"
-            "v_cndmask_b32_e32 %[d], %[d], %[x], vcc\n\t"
-            "v_addc_co_u32_e32 %[x], vcc, 0, %[x], vcc"
-            : [d] "=&v"(d), [x] "+v"(X1)
-            : [f] "v"(f), [K] "v"(K), [i] "n"(I)
-            : "vcc");
+    asm volatile(
+        "v_cmp_ne_u32_sdwa vcc, %[f], 0 src0_sel:BYTE_%c[j] src1_sel:DWORD\n\t"
+        "v_sad_u32 %[d], %[K], %[x], %[i]\n\t"
+        "v_cndmask_b32_e32 %[d], %[d], %[x], vcc\n\t"
+        "v_addc_co_u32_e32 %[x], vcc, 0, %[x], vcc"
+        : [d] "=&v"(d), [x] "+v"(X1)
+        : [f] "v"(f), [K] "v"(K), [j] "n"(J), [i] "n"(I)
+        : "vcc");
     return d;
 }
 
@@ -395,42 +375,44 @@ __device__ __attribute__((always_inline)) inline void split_pass_lm(uint32_t a, 
             }
         }
     }
-    // bits past the symbol width (a key above a narrow symbol) are 0
-    const uint32_t mask = bp >= 8 * EB ? 0u
-                          : EB == 1  ? 0x01010101u << bp
-                          : EB == 2  ? 0x00010001u << bp
-                                     : 1u << bp;
-    uint32_t f[4][NW];
+    // The flags: per 4 symbols one word whose byte j is nonzero iff symbol j's
+    // bit bp is set.  For wider symbols, the byte of each symbol that holds
+    // bit bp is gathered first (v_perm_b32: one per 4 16-bit symbols, two and
+    // an OR per 4 32-bit ones).  Bits past the symbol width (a key above a
+    // narrow symbol) are 0.
+    const uint32_t m8 = bp >= 8 * EB ? 0u : 0x01010101u << (bp & 7);
+    const uint32_t kb = (bp >> 3) & 3u;  // the byte of a symbol that holds bit bp
+    uint32_t f[4][2];
 #pragma unroll
-    for (uint32_t b = 0; b < 4; b++)
+    for (uint32_t b = 0; b < 4; b++) {
+        if constexpr (EB == 1) {
+            f[b][0] = q[b][0] & m8;
+            f[b][1] = q[b][1] & m8;
+        } else if constexpr (EB == 2) {
+            // symbols 2w, 2w+1 in word w: byte kb of symbol s is byte 2 s + kb
+            // of the word pair
+            const uint32_t sel = kb | ((2u + kb) << 8) | ((4u + kb) << 16) | ((6u + kb) << 24);
+            f[b][0] = __builtin_amdgcn_perm(q[b][1], q[b][0], sel) & m8;
+            f[b][1] = __builtin_amdgcn_perm(q[b][3], q[b][2], sel) & m8;
+        } else {
+            // symbol s in word s; selector byte 12 gives a zero byte
+            const uint32_t lo = kb | ((4u + kb) << 8) | 0x0C0C0000u;
+            const uint32_t hi = 0x00000C0Cu | (kb << 16) | ((4u + kb) << 24);
 #pragma unroll
-        for (uint32_t w = 0; w < NW; w++) f[b][w] = q[b][w] & mask;
-    // the lane's byte of the level word in each block (bit j: symbol j), and
-    // its count
+            for (uint32_t h = 0; h < 2; h++)
+                f[b][h] = (__builtin_amdgcn_perm(q[b][4 * h + 1], q[b][4 * h], lo) |
+                           __builtin_amdgcn_perm(q[b][4 * h + 3], q[b][4 * h + 2], hi)) & m8;
+        }
+    }
+    // the lane's byte of the level word in each block (bit j: symbol j), by
+    // two 4-way dot products of the flag bytes with 2^j, and its count
     uint32_t cnt[4];
     lds_u8 *lvl = (lds_u8 *)(uintptr_t)(uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint64_t *)sm.bits[a];
     const uint32_t bsh = bp & 7;
 #pragma unroll
     for (uint32_t b = 0; b < 4; b++) {
-        uint32_t w;
-        if constexpr (EB == 1) {
-            // flag bytes times 2^j, summed by two 4-way dot products
-            w = __builtin_amdgcn_udot4(f[b][0], 0x08040201u,
-                                       __builtin_amdgcn_udot4(f[b][1], 0x80402010u, 0u, false), false) >> bsh;
-        } else if constexpr (EB == 2) {
-            // the flag sits in byte 0 / 2 (bp < 8) or 1 / 3 (bp >= 8) of a word
-            const uint32_t up = bp >= 8 ? 8u : 0u;
-            uint32_t acc = 0;
-#pragma unroll
-            for (uint32_t wd = 0; wd < 4; wd++)
-                acc = __builtin_amdgcn_udot4(f[b][wd], ((1u << (2 * wd)) | (1u << (2 * wd + 1 + 16))) << up, acc,
-                                             false);
-            w = acc >> bsh;
-        } else {
-            w = 0;
-#pragma unroll
-            for (uint32_t j = 0; j < 8; j++) w |= (f[b][j] >> bp) << j;
-        }
+        const uint32_t w = __builtin_amdgcn_udot4(f[b][0], 0x08040201u,
+                                                  __builtin_amdgcn_udot4(f[b][1], 0x80402010u, 0u, false), false) >> bsh;
         cnt[b] = __builtin_popcount(w);
         lvl[64 * b + lane] = (uint8_t)w;
     }
@@ -467,8 +449,7 @@ __device__ __attribute__((always_inline)) inline void split_pass_lm(uint32_t a, 
         }
         static_for<0, 8>([&](auto jj) {
             constexpr uint32_t j = decltype(jj)::value;
-            constexpr uint32_t fw = (j * EB) / 4, part = (EB == 4) ? 0u : (j % (4 / EB));
-            const uint32_t pos = split_step<EB, part, j>(f[b][fw], K, X1);
+            const uint32_t pos = split_step<j % 4, j>(f[b][j / 4], K, X1);
             put_elem<E, j>(EB == 1 ? pos : abase + pos * EB, q[b], sq);
         });
     }
