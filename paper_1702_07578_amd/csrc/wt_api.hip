@@ -18,6 +18,9 @@ static inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a
 static inline uint64_t cdiv64(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 
 static inline uint64_t words_per_level(uint64_t n) { return align_up(cdiv64(n, 64), 8); }
+// directory chunks of a level of nb 512-bit blocks: at least one, which also
+// writes the level's final rank entry when the level is empty
+static inline uint32_t dir_chunks_of(uint64_t nb) { return (uint32_t)std::max<uint64_t>(1, cdiv64(nb, kDirChunk)); }
 static inline uint64_t rank_stride(uint64_t n) { return align_up(words_per_level(n) / 8 + 1, 16); }
 static inline uint64_t sel_stride(uint64_t n) { return align_up(cdiv64(n, WT_SEL_SPACING) + 1, 16); }
 
@@ -110,7 +113,7 @@ static int plan_text(uint64_t n, uint32_t b, uint32_t L, uint32_t kind, const wt
     d.nb = d.W / 8;
     d.rank_stride = rank_stride(n);
     d.sel_stride = sel_stride(n);
-    d.dir_chunks = (uint32_t)cdiv64(d.nb, kDirChunk);
+    d.dir_chunks = dir_chunks_of(d.nb);
 
     const uint64_t nk = 1ull << K;
     const bool deep_wt = (kind == WT_TREE && d.G > 1);
@@ -588,7 +591,7 @@ static uint64_t conv_plan(uint64_t n, uint32_t L, uint8_t *base, ConvWs *w)
     const uint64_t ulen = n + (1ull << L);
     const uint64_t nb = words_per_level(n) / 8, nbu = words_per_level(ulen) / 8;
     const uint64_t bc = std::max<uint64_t>((uint64_t)L * nb, nbu);
-    const uint64_t cs = std::max<uint64_t>((uint64_t)L * cdiv64(nb, kDirChunk), cdiv64(nbu, kDirChunk));
+    const uint64_t cs = std::max<uint64_t>((uint64_t)L * dir_chunks_of(nb), dir_chunks_of(nbu));
     uint64_t off = 0;
     auto take = [&](uint64_t bytes) {
         const uint64_t o = off;
@@ -637,7 +640,7 @@ static TextDesc dir_desc(uint64_t n, uint32_t levels, uint64_t *bits, uint32_t *
     d.nb = d.W / 8;
     d.rank_stride = rank_stride(n);
     d.sel_stride = sel_stride(n);
-    d.dir_chunks = (uint32_t)cdiv64(d.nb, kDirChunk);
+    d.dir_chunks = dir_chunks_of(d.nb);
     d.bits = bits;
     d.zeros = zeros;
     d.rank_dir = rank_dir;
@@ -703,7 +706,7 @@ static uint64_t merge_plan(uint64_t n, uint32_t L, uint32_t count, uint8_t *base
     const uint64_t o_v = take((uint64_t)count * sizeof(wt_levels));
     const uint64_t o_desc = take(sizeof(TextDesc));
     const uint64_t o_bc = take((uint64_t)L * nb * 2);
-    const uint64_t o_cs = take((uint64_t)L * cdiv64(nb, kDirChunk) * 4);
+    const uint64_t o_cs = take((uint64_t)L * dir_chunks_of(nb) * 4);
     if (w) {
         w->tab = (uint32_t *)(base + o_tab);
         w->desc = (TextDesc *)(base + o_desc);
@@ -795,7 +798,7 @@ static uint64_t ps_plan(uint64_t n, uint32_t b, uint32_t L, uint8_t *base, PsWs 
     };
     const uint64_t o_desc = take(sizeof(TextDesc));
     const uint64_t o_bc = take((uint64_t)L * nb * 2);
-    const uint64_t o_cs = take((uint64_t)L * cdiv64(nb, kDirChunk) * 4);
+    const uint64_t o_cs = take((uint64_t)L * dir_chunks_of(nb) * 4);
     const uint64_t o_h0 = take(((uint64_t)P << L) * 4);
     const uint64_t o_h1 = take(((uint64_t)P << L) * 4);
     const uint64_t o_bs = take(4096 * 4);

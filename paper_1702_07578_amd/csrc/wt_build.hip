@@ -466,7 +466,7 @@ __global__ __launch_bounds__(256) void k_gather(const TextDesc *__restrict__ des
     uint32_t ti = find_text_block(bases, nd, nitems, ends), l = 0, np = 1;
     uint64_t w0 = 0;
     const TextDesc *dp = nullptr;
-    const uint32_t *tab = nullptr;
+    const gmem<uint32_t> *tab = nullptr;
     if (ok) {
         dp = &descs[ti];
         const uint64_t idx = item - item_base(bases, nd, ti);
@@ -477,7 +477,7 @@ __global__ __launch_bounds__(256) void k_gather(const TextDesc *__restrict__ des
             ok = l < dp->L;
             w0 = (idx % Wg) * kGatherWords;
             np = 1u << l;
-            tab = dp->walk + walk_off(dp->K, l);
+            tab = gp(dp->walk + walk_off(dp->K, l));
         }
     }
     // largest p in [a, b) with wt_start[p] <= pos (wt_start[a] <= pos)
@@ -518,8 +518,8 @@ __global__ __launch_bounds__(256) void k_gather(const TextDesc *__restrict__ des
         ra = b_p[0];
         rb = b_p[1] + 1;
     }
-    uint64_t *out = d.bits + (uint64_t)l * d.W;
-    const uint64_t *wm = d.tmp_bits + (uint64_t)(l - d.K) * d.W;
+    gmem<uint64_t> *out = gp(d.bits + (uint64_t)l * d.W);
+    const gmem<uint64_t> *wm = gp(d.tmp_bits + (uint64_t)(l - d.K) * d.W);
     uint32_t lo = np;  // interval of the previous piece (none yet)
     for (uint32_t k = 0; k < kGatherWords; k++) {
         const uint64_t ws = (w0 + k) << 6;

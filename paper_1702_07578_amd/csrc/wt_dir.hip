@@ -5,9 +5,10 @@
 //   rank_dir[j]  ones in bits [0, 512 j) of the level, j = 0 .. W/8;
 //   sel_b[q]     index of the 512-bit block that holds the (4096 q + 1)-th b
 //                among positions < n; 0xFFFFFFFF for q past the last sample.
-// Built in three launches per set of levels: ones per block (and per chunk of
-// 1024 blocks), a scan of the chunk sums per level, and the block scan that
-// writes rank_dir and the select samples.
+// Built in two launches per set of levels: ones per block and per chunk of
+// 1024 blocks (and the select samples reset), then the block scan that
+// writes rank_dir and the select samples, each chunk adding up the counts of
+// the chunks before it.
 #include "wt_device.h"
 
 namespace wtg {
@@ -82,46 +83,19 @@ __global__ __launch_bounds__(256) void k_dir_count(const TextDesc *__restrict__ 
             for (uint32_t i = 0; i < 256 / 64; i++) s += red[i];
             gp(d.dir_cs)[(uint64_t)l * d.dir_chunks + c] = s;
         }
-        __syncthreads();
-    }
-}
-
-// per (text, level): exclusive scan of the chunk sums, final rank entry, and
-// select sample arrays reset to "absent"
-__global__ __launch_bounds__(1024) void k_dir_scan(const TextDesc *__restrict__ descs, uint32_t nd,
-                                                   uint32_t tmp)
-{
-    __shared__ uint32_t wsum[1024 / 64];
-    const TextDesc &d = descs[blockIdx.x];
-    const uint32_t l = blockIdx.y;
-    if (l >= dir_levels(d, tmp)) return;
-    uint32_t *cs = d.dir_cs + (uint64_t)l * d.dir_chunks;
-    const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    uint32_t carry = 0;
-    for (uint32_t base = 0; base < d.dir_chunks; base += 1024) {
-        const uint32_t i = base + tid;
-        const uint32_t x = i < d.dir_chunks ? cs[i] : 0u;
-        const uint32_t incl = wave_incl_scan(x);
-        if (lane == 63) wsum[w] = incl;
-        __syncthreads();
-        uint32_t pre = carry;
-        uint32_t tot = 0;
-        for (uint32_t ww = 0; ww < 1024 / 64; ww++) {
-            if (ww < w) pre += wsum[ww];
-            tot += wsum[ww];
+        // the chunk's share of the level's select samples reset to "absent"
+        // (the directory write sets the sampled ones)
+        if (!tmp) {
+            const uint32_t per = (uint32_t)((d.sel_stride + d.dir_chunks - 1) / d.dir_chunks);
+            const uint64_t q0 = (uint64_t)c * per, q1 = min((uint64_t)d.sel_stride, q0 + per);
+            gmem<uint32_t> *s0 = gp(d.sel0 + (uint64_t)l * d.sel_stride);
+            gmem<uint32_t> *s1 = gp(d.sel1 + (uint64_t)l * d.sel_stride);
+            for (uint64_t q = q0 + threadIdx.x; q < q1; q += 256) {
+                s0[q] = 0xFFFFFFFFu;
+                s1[q] = 0xFFFFFFFFu;
+            }
         }
-        if (i < d.dir_chunks) cs[i] = pre + incl - x;
-        carry += tot;
         __syncthreads();
-    }
-    if (tid == 0) dir_rank(d, tmp, l)[d.nb] = carry;
-    if (!tmp) {
-        uint32_t *s0 = d.sel0 + (uint64_t)l * d.sel_stride;
-        uint32_t *s1 = d.sel1 + (uint64_t)l * d.sel_stride;
-        for (uint64_t q = tid; q < d.sel_stride; q += 1024) {
-            s0[q] = 0xFFFFFFFFu;
-            s1[q] = 0xFFFFFFFFu;
-        }
     }
 }
 
@@ -130,7 +104,7 @@ __global__ __launch_bounds__(256) void k_dir_write(const TextDesc *__restrict__ 
                                                    const uint32_t *__restrict__ bases, uint32_t nd,
                                                    uint32_t nitems, uint32_t tmp)
 {
-    __shared__ uint32_t wsum[256 / 64];
+    __shared__ uint32_t wsum[256 / 64], wbefore[256 / 64];
     for (uint32_t item = blockIdx.x; item < nitems; item += gridDim.x) {
         const uint32_t ti = find_text(bases, nd, item);
         const TextDesc &d = descs[ti];
@@ -149,10 +123,26 @@ __global__ __launch_bounds__(256) void k_dir_write(const TextDesc *__restrict__ 
             v[r] = (j0 + r < d.nb) ? gp(bc)[j0 + r] : 0u;
             s += v[r];
         }
+        // ones of the level before this chunk: the sum of the earlier chunks'
+        // counts, added up by the whole block
+        const gmem<uint32_t> *cs = gp(d.dir_cs + (uint64_t)l * d.dir_chunks);
+        uint32_t before = 0;
+        for (uint32_t i = tid; i < c; i += 256) before += cs[i];
+        before = wave_incl_scan(before);
         const uint32_t incl = wave_incl_scan(s);
-        if (lane == 63) wsum[w] = incl;
+        if (lane == 63) {
+            wsum[w] = incl;
+            wbefore[w] = before;
+        }
         __syncthreads();
-        uint32_t pre = gp(d.dir_cs)[(uint64_t)l * d.dir_chunks + c];
+        uint32_t pre = 0;
+        for (uint32_t ww = 0; ww < 256 / 64; ww++) pre += wbefore[ww];
+        // the last chunk also writes the level's final rank entry (its total)
+        if (c + 1 == d.dir_chunks && tid == 0) {
+            uint32_t all = pre;
+            for (uint32_t ww = 0; ww < 256 / 64; ww++) all += wsum[ww];
+            gp(rd)[d.nb] = all;
+        }
         for (uint32_t ww = 0; ww < w; ww++) pre += wsum[ww];
         pre += incl - s;
         uint32_t *s0 = d.sel0 + (uint64_t)l * d.sel_stride;
@@ -194,9 +184,6 @@ hipError_t launch_dirs(const TextDesc *d_descs, const uint32_t *bases, uint32_t 
                            nitems, (uint32_t)tmp);
         if (ctx.after) ctx.after(ctx.user, KID_DIR_COUNT);
     }
-    hipLaunchKernelGGL(k_dir_scan, dim3(nd, max_levels), dim3(1024), 0, ctx.stream, d_descs, nd,
-                       (uint32_t)tmp);
-    if (ctx.after) ctx.after(ctx.user, KID_DIR_SCAN);
     if (nitems) {
         uint32_t grid = (grid_cap && nitems > grid_cap) ? grid_cap : nitems;
         hipLaunchKernelGGL(k_dir_write, dim3(grid), dim3(256), 0, ctx.stream, d_descs, bases, nd,
