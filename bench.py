@@ -211,6 +211,15 @@ def pair_measure(B, d_text, n, b, L, steps, warmup, stream, dev, wt_s=None, wm_s
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
+    # the same steps without an event after every launch (for short texts
+    # the recording itself is a visible part of the step)
+    p0, p1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    p0.record(stream)
+    for _ in range(steps):
+        B.pair_build(d_text, n, b, L, ws=pws, out=(wt_s, wm_s))
+    p1.record(stream)
+    torch.cuda.synchronize()
+    ms_plain = p0.elapsed_time(p1) / steps
     kt = rec.kernel_times(e0)
     pk = {name: {"launches": len(v), "avg_ms": sum(v) / len(v)} for name, v in kt.items()}
     for s in (wt_s, wm_s):
@@ -227,7 +236,8 @@ def pair_measure(B, d_text, n, b, L, steps, warmup, stream, dev, wt_s=None, wm_s
     b_alg_build = 2 * n * b + L * W * 8 + dir_bytes
     build_gbs = 2 * b_alg_build / (ms / 1e3) / 1e9
     del pws
-    return ({"ms_per_step": ms, "value": 2 * n / (ms / 1e3), "kernels": pk, "b_alg_build": b_alg_build,
+    return ({"ms_per_step": ms, "ms_per_step_unrecorded": ms_plain, "value": 2 * n / (ms / 1e3), "kernels": pk,
+             "b_alg_build": b_alg_build,
              "build_alg_gbs": build_gbs,
              "scatter": {"kernel": ("scatter (pair: WT and WM runs from one set of splits)" if L <= 8 else
                                     "scatter (the WM's groups; the WT is gathered from the WM)"),
@@ -271,6 +281,7 @@ def config_line(B, name, steps, warmup, stream, dev, steady_args=None):
     out = {"workload": f"{name}: {WORKLOAD_TEXT.get(name, 'text')}, n={n} uint{8 * b} symbols, {L} levels",
            "n": n, "sym_bytes": b, "lg_sigma": L, "steps": steps,
            "ms_per_step": round(rec["ms_per_step"], 4), "symbols_per_s": round(rec["value"], 1),
+           "ms_per_step_unrecorded": round(rec["ms_per_step_unrecorded"], 4),
            "build_alg_gbs": round(rec["build_alg_gbs"], 1),
            "build_alg_frac": round(rec["build_alg_gbs"] / HBM_PEAK_GBS, 4),
            "scatter": {"kernel": sc["kernel"], "avg_launch_ms": round(sc["avg_launch_ms"], 4),
@@ -740,7 +751,8 @@ def main():
         prec, _, _ = pair_measure(B, d_text, n, b, L, args.steps, args.warmup, stream, dev,
                                   structs[B.WT_TREE], structs[B.WT_MATRIX])
         sc = prec["scatter"]
-        pair = {"ms_per_step": prec["ms_per_step"], "value": prec["value"], "kernels": prec["kernels"],
+        pair = {"ms_per_step": prec["ms_per_step"], "ms_per_step_unrecorded": prec["ms_per_step_unrecorded"],
+                "value": prec["value"], "kernels": prec["kernels"],
                 "roofline": {"kernel": sc["kernel"],
                              **(bound_fields(args.workload, sc["ms_per_step"]) if not args.n else
                                 {"bound": "hbm", "limiter": "not measured at this text length"}),
@@ -927,6 +939,9 @@ def main():
         "conversion": conv,
         "sort_strategy": ps_ms,
         "separate_builds": separate if pair is not None else None,
+        # the same pair steps without the per-launch events the timed region
+        # records (value and the kernel durations come from the recorded ones)
+        "ms_per_step_unrecorded": round(pair["ms_per_step_unrecorded"], 4) if pair is not None else None,
     }
     if args.workload == "uniform256" and not args.n and args.steady_texts:
         # the small configuration: its step above is the isolated latency; this

@@ -59,7 +59,6 @@ struct WaveSmem {
         E elem[kWaveTile];  // the tile, in its next order (loading and splits)
         struct {            // copy-out, after the splits
             uint8_t kw[kWordsB];   // run of every full word
-            uint16_t wb[kRunsB];   // first full word of every run, all levels
             // per run: its first full word's bit in the level streams and
             // its word on the output, each minus (64 or 1) x its first word
             // number, so that word q of the numbering takes bit rec.x + 64 q
@@ -83,7 +82,7 @@ __device__ inline void wave_sync()
 }
 
 // exclusive scan of n <= 64 PER values by one wave, PER consecutive values
-// per lane; get(i) / put(i, x); returns the total
+// per lane; get(i) / put(i, x, value i); returns the total
 template <uint32_t PER, typename Get, typename Put>
 __device__ inline uint32_t wave_exscan_n(uint32_t n, Get get, Put put)
 {
@@ -101,7 +100,7 @@ __device__ inline uint32_t wave_exscan_n(uint32_t n, Get get, Put put)
 #pragma unroll
     for (uint32_t r = 0; r < PER; r++) {
         const uint32_t i = lane * PER + r;
-        if (i < n) put(i, ex);
+        if (i < n) put(i, ex, v[r]);
         ex += v[r];
     }
     return last_lane(incl);
@@ -209,43 +208,39 @@ __device__ __attribute__((always_inline)) inline void copy_full_words(const Text
     const uint32_t nr = lvl_off(Kg);
     const uint32_t *G = sd.G;
     const uint32_t W = (uint32_t)d.W;
+    constexpr uint32_t kWords = KB * kChunks;  // words of one tile, all levels
+    static_assert(kWords % 4 == 0 && kWords / 4 <= 64, "one dword of the word table per lane");
+    // run of every word: the run whose first word it is, 0 elsewhere
+    if (lane < kWords / 4) ((uint32_t *)sm.co.kw)[lane] = 0u;
+    wave_sync();
     const uint32_t total = wave_exscan_n<WaveSmem<E, REORDER, PAIR, KB>::kScanPer>(
         nr, [&](uint32_t e) { return full_words(G[e], sm.h[e], W); },
-        [&](uint32_t e, uint32_t x) {
+        [&](uint32_t e, uint32_t x, uint32_t cnt) {
             const uint32_t a = level_of(e), gs = G[e], gw = (gs + 63) >> 6;
-            sm.co.wb[e] = (uint16_t)x;
             sm.co.rec[e] = make_uint2(a * kWaveTile + sm.lo[e] + ((gw << 6) - gs) - 64u * x,
                                       sm.lvw[a] + gw - x);
+            if (cnt != 0) sm.co.kw[x] = (uint8_t)e;
         });
-    // run of every word: the run whose first word it is, carried forward
-    for (uint32_t q = lane; q < total; q += 64) sm.co.kw[q] = 0;
     wave_sync();
-    for (uint32_t e = lane; e < nr; e += 64)
-        if (full_words(G[e], sm.h[e], W) != 0) sm.co.kw[sm.co.wb[e]] = (uint8_t)e;
-    wave_sync();
-    constexpr uint32_t PER = (KB * kChunks + 63) / 64;
-    uint32_t m = 0;
+    // the lane's words q = lane + 64 i: the run carried forward to each (the
+    // largest run index at or before q, scanned row by row), then the stores
+    constexpr uint32_t NQ = (kWords + 63) / 64;
+    uint32_t rq[NQ], carry = 0;
 #pragma unroll
-    for (uint32_t i = 0; i < PER; i++) {
-        const uint32_t q = lane * PER + i;
-        if (q < total) m = max(m, (uint32_t)sm.co.kw[q]);
+    for (uint32_t i = 0; i < NQ; i++) {
+        const uint32_t q = lane + 64 * i;
+        const uint32_t k = q < total ? (uint32_t)sm.co.kw[q] : 0u;
+        rq[i] = max(wave_incl_max(k), carry);
+        carry = last_lane(rq[i]);
     }
-    // carry: the maximum over the lanes below
-    uint32_t run = wave_incl_max(m);
-    run = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)run, 0x138, 0xf, 0xf, false);  // wave_shr:1
-#pragma unroll
-    for (uint32_t i = 0; i < PER; i++) {
-        const uint32_t q = lane * PER + i;
-        if (q < total) {
-            run = max(run, (uint32_t)sm.co.kw[q]);
-            sm.co.kw[q] = (uint8_t)run;
-        }
-    }
-    wave_sync();
     uint64_t *base = sd.base;
-    for (uint32_t q = lane; q < total; q += 64) {
-        const uint2 r = sm.co.rec[sm.co.kw[q]];
-        gp(base)[r.y + q] = stream64(&sm.bits[0][0], r.x + 64u * q);
+#pragma unroll
+    for (uint32_t i = 0; i < NQ; i++) {
+        const uint32_t q = lane + 64 * i;
+        if (q < total) {
+            const uint2 r = sm.co.rec[rq[i]];
+            gp(base)[r.y + q] = stream64(&sm.bits[0][0], r.x + 64u * q);
+        }
     }
     wave_sync();
 }
@@ -559,7 +554,7 @@ __device__ __attribute__((always_inline)) inline void wave_tile(const TextDesc &
         return x;
     };
     wave_exscan_n<WaveSmem<E, REORDER, PAIR, KB>::kScanPer>(
-        nk, key_count, [&](uint32_t k, uint32_t x) { P[k] = (uint16_t)x; });
+        nk, key_count, [&](uint32_t k, uint32_t x, uint32_t) { P[k] = (uint16_t)x; });
     if (lane == 0) P[nk] = (uint16_t)len;
     if (REORDER)
         for (uint32_t k = lane; k < nk; k += 64) sm.hK[k] = (uint16_t)key_count(k);
@@ -580,14 +575,14 @@ __device__ __attribute__((always_inline)) inline void wave_tile(const TextDesc &
             const uint32_t a = level_of(i + 1);
             return (uint32_t)sm.h[lvl_off(a) + rev_bits(i + 1 - lvl_off(a), a)];
         },
-        [&](uint32_t i, uint32_t x) {
+        [&](uint32_t i, uint32_t x, uint32_t) {
             const uint32_t a = level_of(i + 1);
             sm.lo[lvl_off(a) + rev_bits(i + 1 - lvl_off(a), a)] = (uint16_t)(x - (a - 1) * len);
         });
     if (REORDER)
         wave_exscan_n<WaveSmem<E, REORDER, PAIR, KB>::kScanPer>(
             nk, [&](uint32_t i) { return (uint32_t)sm.hK[rev_bits(i, Kg)]; },
-            [&](uint32_t i, uint32_t x) { sm.loK[rev_bits(i, Kg)] = (uint16_t)x; });
+            [&](uint32_t i, uint32_t x, uint32_t) { sm.loK[rev_bits(i, Kg)] = (uint16_t)x; });
     wave_sync();
 
     // 4. split by one bit at a time; each pass's bits are level a in the
