@@ -247,43 +247,51 @@ __device__ __attribute__((always_inline)) inline void copy_full_words(const Text
 
 // First and last word of every run (one lane per run, all levels): merged
 // with the word kept from earlier tiles of the range, stored when complete,
-// kept otherwise.
-template <typename E, bool REORDER, bool PAIR, uint32_t KB>
+// kept otherwise.  The pair does both of its outputs in the same pass over
+// the runs (the run's length, its place in the streams and its first 64
+// bits are the same for both).
+template <uint32_t NS, typename E, bool REORDER, bool PAIR, uint32_t KB>
 __device__ __attribute__((always_inline)) inline void run_end_words(const TextDesc &d, uint32_t Kg,
                                                                     WaveSmem<E, REORDER, PAIR, KB> &sm,
-                                                                    const Side &sd)
+                                                                    const Side (&sides)[NS])
 {
-    uint64_t *base = sd.base;
     const uint32_t W = (uint32_t)d.W;
     for (uint32_t e = lane_id(); e < lvl_off(Kg); e += 64) {
         const uint32_t hh = sm.h[e];
         if (hh == 0) continue;
         const uint32_t a = level_of(e);
         const uint32_t sb = a * kWaveTile + sm.lo[e];  // the run's first bit in the streams
-        // positions are below n < 2^32; ge may equal n
-        const uint32_t gs = sd.G[e], ge = gs + hh;
-        const uint32_t fw = gs >> 6, lw = (ge - 1) >> 6;
-        const uint32_t off = gs & 63;
-        // the first word, when the run does not cover it from its bit 0
-        // to its top (the full words are stored by copy_full_words)
-        const bool head = off != 0 || hh < 64;
-        const uint32_t cnt = min(hh, 64u - off);  // bits of the run in word fw
-        uint64_t hv = low_bits(stream64(&sm.bits[0][0], sb), cnt) << off;
-        const uint8_t pw = sd.pend[e];
-        const bool merge = off != 0 && pw != kNoPend;  // the kept word is fw
-        if (merge) hv |= sd.pend_v[e];
-        const bool lowok = off == 0 || pw == kPend;
-        const bool head_full = off + cnt == 64;
-        if (head && head_full && fw < W) {
-            if (lowok) gp(base)[sm.lvw[a] + fw] = hv;
-            else gatomic_or(&base[sm.lvw[a] + fw], hv);
+        const uint64_t first = stream64(&sm.bits[0][0], sb);
+        const uint32_t lvw = sm.lvw[a];
+#pragma unroll
+        for (uint32_t k = 0; k < NS; k++) {
+            const Side &sd = sides[k];
+            uint64_t *base = sd.base;
+            // positions are below n < 2^32; ge may equal n
+            const uint32_t gs = sd.G[e], ge = gs + hh;
+            const uint32_t fw = gs >> 6, lw = (ge - 1) >> 6;
+            const uint32_t off = gs & 63;
+            // the first word, when the run does not cover it from its bit 0
+            // to its top (the full words are stored by copy_full_words)
+            const bool head = off != 0 || hh < 64;
+            const uint32_t cnt = min(hh, 64u - off);  // bits of the run in word fw
+            uint64_t hv = low_bits(first, cnt) << off;
+            const uint8_t pw = sd.pend[e];
+            const bool merge = off != 0 && pw != kNoPend;  // the kept word is fw
+            if (merge) hv |= sd.pend_v[e];
+            const bool lowok = off == 0 || pw == kPend;
+            const bool head_full = off + cnt == 64;
+            if (head && head_full && fw < W) {
+                if (lowok) gp(base)[lvw + fw] = hv;
+                else gatomic_or(&base[lvw + fw], hv);
+            }
+            // the last word, when it is not the first and the run ends inside it
+            const bool tail = lw != fw && (ge & 63) != 0;
+            const uint64_t tv = low_bits(stream64(&sm.bits[0][0], sb + ((lw << 6) - gs)), (ge - 1) % 64 + 1);
+            const bool keep_head = head && !head_full;
+            sd.pend[e] = tail ? kPend : (keep_head ? (lowok ? kPend : kPendForeign) : kNoPend);
+            sd.pend_v[e] = tail ? tv : (keep_head ? hv : 0ull);
         }
-        // the last word, when it is not the first and the run ends inside it
-        const bool tail = lw != fw && (ge & 63) != 0;
-        const uint64_t tv = low_bits(stream64(&sm.bits[0][0], sb + ((lw << 6) - gs)), (ge - 1) % 64 + 1);
-        const bool keep_head = head && !head_full;
-        sd.pend[e] = tail ? kPend : (keep_head ? (lowok ? kPend : kPendForeign) : kNoPend);
-        sd.pend_v[e] = tail ? tv : (keep_head ? hv : 0ull);
     }
 }
 
@@ -612,12 +620,14 @@ __device__ __attribute__((always_inline)) inline void wave_tile(const TextDesc &
     //    the WM's)
     const Side s1{sm.G, sm.pend, sm.pend_v, group_base(d, g)};
     copy_full_words(d, Kg, sm, s1);
-    run_end_words(d, Kg, sm, s1);
-    if (PAIR) {
-        wave_sync();
+    if constexpr (PAIR) {
         const Side s2{sm.G2, sm.pend2, sm.pend_v2, d.bits2};
         copy_full_words(d, Kg, sm, s2);
-        run_end_words(d, Kg, sm, s2);
+        const Side both[2] = {s1, s2};
+        run_end_words(d, Kg, sm, both);
+    } else {
+        const Side one[1] = {s1};
+        run_end_words(d, Kg, sm, one);
     }
     wave_sync();
     // the next tile's runs start where this tile's end
