@@ -248,14 +248,20 @@ def pair_measure(B, d_text, n, b, L, steps, warmup, stream, dev, wt_s=None, wm_s
 
 
 def bound_fields(workload, scatter_ms_per_step):
-    """What bounds the scatter: vector-instruction issue when the committed
-    counters of this kernel source measure it (achieved against the issue
-    rate under "alu"), else not measured.  The roofline's own figures stay
-    algorithmic bytes against the HBM peak."""
+    """What bounds the scatter, from the committed counters of this kernel
+    source: vector-instruction issue ("alu") when it runs at half the chip's
+    issue rate or more, else latency (neither the issue rate nor HBM is
+    saturated); the issue figures go under "alu".  Without matching counters
+    the limiter is not measured.  The roofline's own figures stay algorithmic
+    bytes against the HBM peak."""
     alu = alu_issue(workload, scatter_ms_per_step)
     if alu is None:
         return {"bound": "hbm", "limiter": "not measured on this kernel source (no matching instruction counters)"}
-    return {"bound": "alu", "alu": alu}
+    if alu["frac"] >= 0.5:
+        return {"bound": "alu", "alu": alu}
+    return {"bound": "latency", "alu": alu,
+            "limiter": "neither the VALU issue rate nor HBM is saturated (dependent LDS round trips and launch "
+                       "latency of short work)"}
 
 
 def config_line(B, name, steps, warmup, stream, dev, steady_args=None):
@@ -608,7 +614,7 @@ def main():
     ap.add_argument("--config-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--step-only", action="store_true",
-                    help="only the pair step (warm-up, one probe step, then the timed steps): the "
+                    help="only the pair step (warm-up, one probe step, then the timed steps twice): the "
                          "launches a counter run profiles")
     ap.add_argument("--tile-log2", type=int, default=0)
     ap.add_argument("--group-bits", type=int, default=0)
@@ -663,11 +669,12 @@ def main():
         log("copy calibration: 3 x bitwise_not over 2^28 int32 (1 GiB read + 1 GiB write each)")
     d_text = B.to_device(text, dev)
     if args.step_only:
-        # warm-up steps, one probe step and the timed steps of the pair build,
-        # nothing else: (warmup + 1 + steps) pair builds in all
+        # warm-up steps, one probe step and the timed steps (recorded, then
+        # unrecorded) of the pair build, nothing else: warmup + 1 + 2 steps
+        # pair builds in all
         rec, _, _ = pair_measure(B, d_text, n, b, L, args.steps, args.warmup, stream, dev)
         print(json.dumps({"workload": args.workload, "n": n, "sym_bytes": b, "lg_sigma": L,
-                          "pair_builds": args.warmup + 1 + args.steps, "ms_per_step": round(rec["ms_per_step"], 4),
+                          "pair_builds": args.warmup + 1 + 2 * args.steps, "ms_per_step": round(rec["ms_per_step"], 4),
                           "scatter_ms_per_step": round(rec["scatter"]["ms_per_step"], 4)}), flush=True)
         return
     tune = B.make_tune(tile_log2=args.tile_log2, group_bits=args.group_bits)
