@@ -567,25 +567,24 @@ __device__ __attribute__((always_inline)) inline void wave_tile(const TextDesc &
     if (REORDER)
         for (uint32_t k = lane; k < nk; k += 64) sm.hK[k] = (uint16_t)key_count(k);
     wave_sync();
-    for (uint32_t e = lane; e < lvl_off(Kg); e += 64) {
-        const uint32_t a = level_of(e), k = e - lvl_off(a), sh = Kg - a;
-        sm.h[e] = (uint16_t)(P[(k + 1) << sh] - P[k << sh]);
-    }
-    wave_sync();
     // 3. start of every key in the tile order of its level (keys in reversed
-    //    order)
+    //    order), with the counts of step 2 taken on the way
     //    One scan runs over levels 1..Kg-1 one after the other: each level's
     //    counts add up to len, so level a starts at (a - 1) len.
-    if (lane == 0) sm.lo[0] = 0;
+    if (lane == 0) {
+        sm.lo[0] = 0;
+        sm.h[0] = (uint16_t)len;
+    }
     wave_exscan_n<WaveSmem<E, REORDER, PAIR, KB>::kScanPer>(
         lvl_off(Kg) - 1,
         [&](uint32_t i) {
-            const uint32_t a = level_of(i + 1);
-            return (uint32_t)sm.h[lvl_off(a) + rev_bits(i + 1 - lvl_off(a), a)];
+            const uint32_t a = level_of(i + 1), k = rev_bits(i + 1 - lvl_off(a), a), sh = Kg - a;
+            return (uint32_t)(P[(k + 1) << sh] - P[k << sh]);
         },
-        [&](uint32_t i, uint32_t x, uint32_t) {
-            const uint32_t a = level_of(i + 1);
-            sm.lo[lvl_off(a) + rev_bits(i + 1 - lvl_off(a), a)] = (uint16_t)(x - (a - 1) * len);
+        [&](uint32_t i, uint32_t x, uint32_t cnt) {
+            const uint32_t a = level_of(i + 1), e = lvl_off(a) + rev_bits(i + 1 - lvl_off(a), a);
+            sm.lo[e] = (uint16_t)(x - (a - 1) * len);
+            sm.h[e] = (uint16_t)cnt;
         });
     if (REORDER)
         wave_exscan_n<WaveSmem<E, REORDER, PAIR, KB>::kScanPer>(
