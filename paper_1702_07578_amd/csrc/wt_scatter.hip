@@ -480,20 +480,25 @@ struct TileUnits {
 template <typename E>
 constexpr bool kPrefetch = sizeof(E) == 1;
 
-template <typename E, bool REORDER, bool PAIR, uint32_t KB>
+template <typename E, bool REORDER, bool PAIR, uint32_t KB, typename EIN>
 __device__ __attribute__((always_inline)) inline void wave_tile(const TextDesc &d, uint32_t g,
                                                                 uint32_t Kg, uint32_t t,
                                                                 WaveSmem<E, REORDER, PAIR, KB> &sm,
-                                                                TileUnits<E> &tu, bool vec,
+                                                                TileUnits<EIN> &tu, bool vec,
                                                                 bool have, uint32_t t1)
 {
+    // KEYS: the text's symbols are wider than the tile's elements, which
+    // hold the group key alone (the last group of a wider text: its key is
+    // the symbol's low Kg <= 8 bits, shift 0)
+    constexpr bool KEYS = sizeof(EIN) != sizeof(E);
+    static_assert(!KEYS || (sizeof(E) == 1 && !REORDER), "keys are bytes, and only the last group drops the symbol");
     const uint32_t lane = lane_id();
     const uint64_t start = (uint64_t)t * kWaveTile;
     const uint32_t len = (uint32_t)min((uint64_t)kWaveTile, d.n - start);
     const bool padded = len < kWaveTile;
     const uint32_t shift = d.L - g * d.K - Kg;
     const uint32_t nk = 1u << Kg, kmask = nk - 1u;
-    const gmem<E> *src = gp((const E *)seq_in(d, g) + start + lane);
+    const gmem<EIN> *src = gp((const EIN *)seq_in(d, g) + start + lane);
     uint32_t *cnt = sm.tmp32();
     uint16_t *P = sm.tmp16();
 
@@ -511,39 +516,66 @@ __device__ __attribute__((always_inline)) inline void wave_tile(const TextDesc &
     if (!padded && vec) {
         // whole tile of a 16-byte aligned sequence: 16-byte units; with
         // prefetch they were loaded during the previous tile
-        if (!kPrefetch<E> || !have) tu.load((const E *)seq_in(d, g) + start);
-        uint4 *eu = (uint4 *)sm.elem;
+        if (!kPrefetch<EIN> || !have) tu.load((const EIN *)seq_in(d, g) + start);
+        if constexpr (!KEYS) {
+            uint4 *eu = (uint4 *)sm.elem;
 #pragma unroll
-        for (uint32_t i = 0; i < TileUnits<E>::kPerLane; i++) eu[i * 64 + lane] = tu.q[i];
-        // the key's bits that lie inside the symbol (the rest are zero)
-        constexpr uint32_t width = 8 * sizeof(E);
-        const uint32_t kw = shift >= width ? 0u : min(Kg, width - shift);
-        const uint32_t ks = shift >= width ? 0u : shift;
+            for (uint32_t i = 0; i < TileUnits<E>::kPerLane; i++) eu[i * 64 + lane] = tu.q[i];
+            // the key's bits that lie inside the symbol (the rest are zero)
+            constexpr uint32_t width = 8 * sizeof(E);
+            const uint32_t kw = shift >= width ? 0u : min(Kg, width - shift);
+            const uint32_t ks = shift >= width ? 0u : shift;
 #pragma unroll
-        for (uint32_t i = 0; i < TileUnits<E>::kPerLane; i++) {
-            const uint32_t w4[4] = {tu.q[i].x, tu.q[i].y, tu.q[i].z, tu.q[i].w};
+            for (uint32_t i = 0; i < TileUnits<E>::kPerLane; i++) {
+                const uint32_t w4[4] = {tu.q[i].x, tu.q[i].y, tu.q[i].z, tu.q[i].w};
 #pragma unroll
-            for (uint32_t j = 0; j < 4; j++)
+                for (uint32_t j = 0; j < 4; j++)
 #pragma unroll
-                for (uint32_t s = 0; s < 4 / sizeof(E); s++)
-                    atomicAdd((uint32_t *)(cnt_lane + (__builtin_amdgcn_ubfe(w4[j], s * width + ks, kw) << csh)), 1u);
+                    for (uint32_t s = 0; s < 4 / sizeof(E); s++)
+                        atomicAdd((uint32_t *)(cnt_lane + (__builtin_amdgcn_ubfe(w4[j], s * width + ks, kw) << csh)),
+                                  1u);
+            }
+        } else {
+            // the low byte of every symbol (v_perm_b32), masked to the key:
+            // 8 keys per unit of 16-bit symbols, 4 per unit of 32-bit ones,
+            // stored at the unit's symbol positions
+            const uint32_t km4 = kmask * 0x01010101u;
+#pragma unroll
+            for (uint32_t i = 0; i < TileUnits<EIN>::kPerLane; i++) {
+                const uint4 u = tu.q[i];
+                uint32_t kq[2];
+                if constexpr (sizeof(EIN) == 2) {
+                    kq[0] = __builtin_amdgcn_perm(u.y, u.x, 0x06040200u) & km4;
+                    kq[1] = __builtin_amdgcn_perm(u.w, u.z, 0x06040200u) & km4;
+                    *(uint2 *)(sm.elem + 8 * (i * 64 + lane)) = make_uint2(kq[0], kq[1]);
+                } else {
+                    kq[0] = (__builtin_amdgcn_perm(u.y, u.x, 0x0C0C0400u) |
+                             __builtin_amdgcn_perm(u.w, u.z, 0x04000C0Cu)) & km4;
+                    *(uint32_t *)(sm.elem + 4 * (i * 64 + lane)) = kq[0];
+                }
+#pragma unroll
+                for (uint32_t j = 0; j < 16 / sizeof(EIN); j++)
+                    atomicAdd((uint32_t *)(cnt_lane + (__builtin_amdgcn_ubfe(kq[j / 4], 8 * (j % 4), 8) << csh)), 1u);
+            }
         }
-        if (kPrefetch<E>) {
+        if (kPrefetch<EIN>) {
             // the next tile of the range, when it is whole
             const uint64_t nstart = start + kWaveTile;
-            if (t + 1 < t1 && nstart + kWaveTile <= d.n) tu.load((const E *)seq_in(d, g) + nstart);
+            if (t + 1 < t1 && nstart + kWaveTile <= d.n) tu.load((const EIN *)seq_in(d, g) + nstart);
         }
     } else {
+        // a key alone keeps only its bits (padding: all ones, after every key)
+        const uint32_t keep = KEYS ? kmask : ~0u;
         uint32_t v[kChunks];
         if (!padded) {
 #pragma unroll
-            for (uint32_t c = 0; c < kChunks; c++) v[c] = src[c * 64];
+            for (uint32_t c = 0; c < kChunks; c++) v[c] = (uint32_t)src[c * 64] & keep;
 #pragma unroll
             for (uint32_t c = 0; c < kChunks; c++) atomicAdd(&cnt[(((v[c] >> shift) & kmask) << cb) | lane_copy], 1u);
         } else {
 #pragma unroll
             for (uint32_t c = 0; c < kChunks; c++)
-                v[c] = (c * 64 + lane < len) ? (uint32_t)src[c * 64] : (uint32_t)(E)~0u;
+                v[c] = (c * 64 + lane < len) ? ((uint32_t)src[c * 64] & keep) : (uint32_t)(E)~0u;
 #pragma unroll
             for (uint32_t c = 0; c < kChunks; c++)
                 if (c * 64 + lane < len) atomicAdd(&cnt[(((v[c] >> shift) & kmask) << cb) | lane_copy], 1u);
@@ -639,7 +671,7 @@ __device__ __attribute__((always_inline)) inline void wave_tile(const TextDesc &
     wave_sync();
 }
 
-template <typename E, bool REORDER, bool PAIR, uint32_t KB>
+template <typename E, bool REORDER, bool PAIR, uint32_t KB, typename EIN>
 __device__ void wave_range(const TextDesc &d, uint32_t g, uint32_t Kg, uint32_t r,
                            WaveSmem<E, REORDER, PAIR, KB> &sm)
 {
@@ -651,10 +683,10 @@ __device__ void wave_range(const TextDesc &d, uint32_t g, uint32_t Kg, uint32_t 
     }
     wave_sync();
     const uint32_t t0 = r * d.R, t1 = min(d.ntiles, t0 + d.R);
-    const E *seq = (const E *)seq_in(d, g);
+    const EIN *seq = (const EIN *)seq_in(d, g);
     const bool vec = ((uintptr_t)seq & 15) == 0;
-    TileUnits<E> tu;
-    for (uint32_t t = t0; t < t1; t++) wave_tile(d, g, Kg, t, sm, tu, vec, t > t0, t1);
+    TileUnits<EIN> tu;
+    for (uint32_t t = t0; t < t1; t++) wave_tile<E, REORDER, PAIR, KB, EIN>(d, g, Kg, t, sm, tu, vec, t > t0, t1);
     // words still open at the end of the range are shared with the next one
     for (uint32_t e = lane; e < lvl_off(Kg); e += 64) {
         if (sm.pend[e] != kNoPend) {
@@ -699,7 +731,7 @@ constexpr uint32_t kScatMinWaves = (sizeof(E) == 1 && PAIR && !REORDER && KB == 
 // Work item = (text, range); wave w of workgroup b takes item b BW + w,
 // then strides by the whole grid.  The REORDER variant takes the texts whose
 // symbols move on to another group after group g.
-template <typename E, bool REORDER, bool PAIR, uint32_t KB>
+template <typename E, bool REORDER, bool PAIR, uint32_t KB, typename EIN = E>
 __global__ __launch_bounds__((scat_block_waves<E, REORDER, PAIR, KB>() * 64)) __attribute__((amdgpu_waves_per_eu(kScatMinWaves<E, REORDER, PAIR, KB>))) void k_scatter(const TextDesc *__restrict__ descs,
                                                              const uint32_t *__restrict__ bases,
                                                              uint32_t nd, uint32_t nitems, uint32_t g)
@@ -711,26 +743,26 @@ __global__ __launch_bounds__((scat_block_waves<E, REORDER, PAIR, KB>() * 64)) __
         const uint32_t ti = find_text(bases, nd, item);
         const TextDesc &d = descs[ti];
         const uint32_t r = item - item_base(bases, nd, ti);
-        if (d.b != sizeof(E) || g >= d.G || r >= d.nranges || (g + 1 < d.G) != REORDER) continue;
+        if (d.b != sizeof(EIN) || g >= d.G || r >= d.nranges || (g + 1 < d.G) != REORDER) continue;
         if ((d.pair != 0 && g == 0) != PAIR) continue;  // pairs' group 0 goes to the pair instantiations
         const uint32_t Kg = group_bits(d, g);
         if (Kg == 0 || Kg > KB) continue;  // the tables hold KB levels (the host picks KB >= Kg)
         if (PAIR && KB == kMaxGroupBits && Kg < KB) continue;  // the 7-bit pair kernel takes those
-        wave_range<E, REORDER, PAIR, KB>(d, g, Kg, r, sm[w]);
+        wave_range<E, REORDER, PAIR, KB, EIN>(d, g, Kg, r, sm[w]);
     }
 }
 
 // one instantiation over all items: one wave per item, or, with a cap, a
 // persistent grid of grid_cap workgroups of four waves (the same number of
 // waves whatever the instantiation's workgroup size)
-template <typename E, bool REORDER, bool PAIR, uint32_t KB>
+template <typename E, bool REORDER, bool PAIR, uint32_t KB, typename EIN = E>
 static void launch_one(const TextDesc *d_descs, const GroupLaunch &gl, const LaunchCtx &ctx)
 {
     constexpr uint32_t BW = scat_block_waves<E, REORDER, PAIR, KB>();
     uint32_t grid = (gl.nranges + BW - 1) / BW;
     const uint32_t cap = gl.grid_cap * (4 / BW);
     if (cap && grid > cap) grid = cap;
-    hipLaunchKernelGGL((k_scatter<E, REORDER, PAIR, KB>), dim3(grid), dim3(BW * 64), 0, ctx.stream, d_descs,
+    hipLaunchKernelGGL((k_scatter<E, REORDER, PAIR, KB, EIN>), dim3(grid), dim3(BW * 64), 0, ctx.stream, d_descs,
                        gl.range_bases, gl.nd, gl.nranges, gl.g);
 }
 
@@ -743,7 +775,8 @@ static void launch_width(const TextDesc *d_descs, const GroupLaunch &gl, const L
     if (gl.g == 0 && (gl.pmask & 4u)) launch_one<E, false, true, K8>(d_descs, gl, ctx);
     if (gl.g == 0 && (gl.pmask & 8u)) launch_one<E, true, true, K8>(d_descs, gl, ctx);
     if (!(gl.pmask & 1u)) return;
-    if (gl.rmask & 1u) launch_one<E, false, false, K8>(d_descs, gl, ctx);
+    // the last group of a text of wider symbols splits its key bytes alone
+    if (gl.rmask & 1u) launch_one<uint8_t, false, false, K8, E>(d_descs, gl, ctx);
     if (gl.rmask & 2u) launch_one<E, true, false, K8>(d_descs, gl, ctx);
 }
 
