@@ -132,6 +132,14 @@ __device__ inline gmem<T> *gp(T *p)
 {
     return (gmem<T> *)p;
 }
+// a 16-byte load marked non-temporal (data read once, which should not
+// displace cache lines that are used again)
+__device__ inline ulonglong2 load_nt(const gmem<ulonglong2> *p)
+{
+    typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
+    const u64x2 v = __builtin_nontemporal_load((const gmem<u64x2> *)p);
+    return make_ulonglong2(v.x, v.y);
+}
 __device__ inline void gatomic_or(uint64_t *p, uint64_t v)
 {
     __hip_atomic_fetch_or(gp(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

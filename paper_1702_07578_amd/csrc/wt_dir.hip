@@ -58,7 +58,7 @@ __global__ __launch_bounds__(256) void k_dir_count(const TextDesc *__restrict__ 
             const uint32_t u = r * 256 + threadIdx.x;
             x[r] = 0;
             if (u < units) {
-                const ulonglong2 v = p[u];
+                const ulonglong2 v = load_nt(p + u);  // each level word is read once here
                 x[r] = __popcll(v.x) + __popcll(v.y);
             }
         }
