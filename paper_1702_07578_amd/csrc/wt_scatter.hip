@@ -4,20 +4,22 @@
 // interval, scanning the text in order, so inside an interval the bits are in
 // text order.  Here every wave owns one range of consecutive tiles and walks
 // it tile by tile, with no barrier shared with other waves.  A tile (at most
-// kWaveTile symbols) sits in the wave's registers, 64 symbols per chunk; it is
-// ordered one bit at a time: after splitting by bits 0..a-1 of the group key
-// (zeros first, stably) the tile is ordered by its reversed a-bit key
-// (Observation 2), so level a's bits of every key form one contiguous run.
-// The ballot of bit a that drives the split of order a is, chunk by chunk,
-// level a of the tile in that order.  The split offsets come from the tile's
-// key counts (one LDS histogram, merged upward), not from a counting pass.
-// Each run is then copied to its interval start on the level (prefix order
-// for the WT, bit-reversed order for the WM; Section 5.1).  Consecutive tiles
-// put a key's runs next to each other, so the word a run ends in is kept in
-// LDS and completed by the next tile's run of that key; only words shared
-// with another range are filled by atomic OR.  With more than one group, the
-// split by the group's last bit writes every symbol straight to its position
-// in the next group's sequence.
+// kWaveTile symbols) sits in the wave's LDS element buffer; it is ordered one
+// bit at a time: after splitting by bits 0..a-1 of the group key (zeros
+// first, stably) the tile is ordered by its reversed a-bit key (Observation
+// 2), so level a's bits of every key form one contiguous run.  Each pass has
+// every lane own 8 consecutive positions of each of the tile's 4 blocks: the
+// lane packs their bits into one byte of level a's stream, and the ones
+// before each of them (its own count plus a wave scan of the lanes' counts)
+// give every symbol its place in the next order.  The tile's key counts (one
+// LDS histogram) give the length of every run and its start in each level's
+// order.  Each run is then copied to its interval start on the level (prefix
+// order for the WT, bit-reversed order for the WM; Section 5.1).  Consecutive
+// tiles put a key's runs next to each other, so the word a run ends in is
+// kept in LDS and completed by the next tile's run of that key; only words
+// shared with another range are filled by atomic OR.  With more than one
+// group, the split by the group's last bit writes every symbol straight to
+// its position in the next group's sequence.
 #include <type_traits>
 
 #include "wt_tiles.h"
