@@ -130,7 +130,7 @@ enum KernelId : uint32_t {
     KID_BORDERS,
     KID_SCATTER,
     KID_DIR_COUNT,
-    KID_DIR_SCAN,
+    KID_DIR_SCAN,  // no longer launched (the chunk scan is part of the write); kept so ids stay stable
     KID_DIR_WRITE,
     KID_WALK,
     KID_GATHER,
