@@ -399,7 +399,9 @@ def run_batch(args):
                                f"one graph-captured sequence of launches", "texts": len(texts),
                    "symbols": total, "tune": {"grid": tune.grid if tune else 0,
                                                "persist": tune.persist if tune else 0}},
-        "roofline": {"kernel": "the whole batched build (every kernel of the graph replay)", "bound": "hbm",
+        "roofline": {"kernel": "the whole batched build (every kernel of the graph replay)", "bound": "latency",
+                     "limiter": "not HBM: the scatter is bound by instruction issue on long texts and the "
+                                "16-level texts' interval walk and gather by dependent loads per prefix",
                      "achieved": round(alg_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(alg_gbs / HBM_PEAK_GBS, 4), "traffic": None,
                      "alg_bytes_per_launch": int(alg), "avg_launch_ms": round(batch_ms, 4)},
