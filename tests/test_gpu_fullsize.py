@@ -149,3 +149,39 @@ def _same_outputs(a, b, n):
             if not torch.equal(region(a, pa + l * stride * 4, cnt, 4), region(b, pb + l * stride * 4, cnt, 4)):
                 return False
     return True
+
+
+def test_markov96_whole_levels_equal_oracle(orc):
+    """The benchmark's step at its full size (2^30 byte symbols, 7 levels),
+    element by element: every level word and Z of both structures of the pair
+    build equal the oracle's (its top-down builder on all host threads, pinned
+    against the sequential one), and every directory entry equals the
+    oracle's directory of those levels."""
+    import torch
+    from paper_1702_07578_amd import inputs
+    B = lib()
+    T, L = inputs.make("markov96")
+    n = T.size
+    print(f"[full-size] markov96 whole levels: n={n} L={L}, oracle on {orc.par_threads()} threads", flush=True)
+    d = B.to_device(T)
+    wt, wm = B.pair_build(d, n, 1, L)
+    torch.cuda.synchronize()
+    del d
+    cap = orc.sel_capacity(n)
+    for kind, s in ((WT, wt), (WM, wm)):
+        assert s.status() == 0
+        bits, zeros, rd, s0, s1 = s.host_arrays()
+        ob, oz = orc.par_build(kind, T, L)
+        W = ob.shape[1]
+        assert np.array_equal(zeros, oz), f"kind {kind}: Z"
+        for l in range(L):
+            if not np.array_equal(bits[l], ob[l]):
+                bad = np.flatnonzero(bits[l] != ob[l])
+                raise AssertionError(f"kind {kind} level {l}: {bad.size} words differ, first {bad[0]}")
+            ord_, os0, os1 = orc.directory(ob[l], n)
+            assert np.array_equal(rd[l][: W // 8 + 1], ord_), f"kind {kind} rank_dir level {l}"
+            assert np.array_equal(s0[l][:cap], os0), f"kind {kind} sel0 level {l}"
+            assert np.array_equal(s1[l][:cap], os1), f"kind {kind} sel1 level {l}"
+        del bits, ob
+    del wt, wm
+    torch.cuda.empty_cache()
