@@ -1,12 +1,14 @@
 """Parity at the workload sizes, in the launch configuration the benchmark
-uses (default tuning): the texts are too long for a whole oracle build, so
-the oracle supplies sampled level bits (its per-position definition), and
-every other output is checked through properties that hold at any size:
-the zero count of every level, the popcount of every level, the padding
-bits, the directories of every level recomputed by the oracle from the
-GPU's level words, and access at sampled positions.  The pair build (both
-structures of the text, the benchmark's step) must write exactly the same
-outputs as the checked separate builds."""
+uses (default tuning), element by element: every level word and Z of the WT
+and the WM equal the oracle's (its top-down builder on all host threads,
+pinned against the sequential one on small texts), and every directory entry
+equals the oracle's directory of those levels.  On top, properties that hold
+at any size: the zero count and popcount of every level against the symbol
+counts, the padding bits, level bits at sampled positions against the
+oracle's per-position definition, access at sampled positions, and rank and
+select against counts and each other.  The pair build (both structures of
+the text, the benchmark's step) must write exactly the same outputs as the
+checked separate builds."""
 import numpy as np
 import pytest
 
@@ -31,6 +33,15 @@ def _check_structure(orc, T, L, kind, s, rng):
     assert s.status() == 0
     bits, zeros, rd, s0, s1 = s.host_arrays()
     W = bits.shape[1]
+    # every word and Z against the oracle's whole build
+    ob, oz = orc.par_build(kind, T, L)
+    assert np.array_equal(zeros, oz), "Z against the oracle"
+    for l in range(L):
+        if not np.array_equal(bits[l], ob[l]):
+            bad = np.flatnonzero(bits[l] != ob[l])
+            raise AssertionError(f"kind {kind} level {l}: {bad.size} words differ from the oracle, "
+                                 f"first {bad[0]}: gpu {bits[l][bad[0]]:#x} oracle {ob[l][bad[0]]:#x}")
+    del ob
     assert np.array_equal(zeros, _zero_counts(T, L)), "zero counts"
     pos = np.sort(rng.integers(0, n, size=SAMPLES, dtype=np.uint64))
     for l in range(L):
@@ -41,7 +52,8 @@ def _check_structure(orc, T, L, kind, s, rng):
         if n % 64:
             assert int(lv[n // 64]) >> (n % 64) == 0, f"level {l} tail bits"
         assert not lv[(n + 63) // 64:].any(), f"level {l} padding words"
-        # directories: the oracle's, recomputed from this level's words
+        # directories: the oracle's, of this level's words (equal to the
+        # oracle's own levels, checked above)
         ord_, os0, os1 = orc.directory(lv, n)
         cap = orc.sel_capacity(n)
         assert np.array_equal(rd[l][: W // 8 + 1], ord_), f"rank_dir level {l}"
@@ -150,38 +162,3 @@ def _same_outputs(a, b, n):
                 return False
     return True
 
-
-def test_markov96_whole_levels_equal_oracle(orc):
-    """The benchmark's step at its full size (2^30 byte symbols, 7 levels),
-    element by element: every level word and Z of both structures of the pair
-    build equal the oracle's (its top-down builder on all host threads, pinned
-    against the sequential one), and every directory entry equals the
-    oracle's directory of those levels."""
-    import torch
-    from paper_1702_07578_amd import inputs
-    B = lib()
-    T, L = inputs.make("markov96")
-    n = T.size
-    print(f"[full-size] markov96 whole levels: n={n} L={L}, oracle on {orc.par_threads()} threads", flush=True)
-    d = B.to_device(T)
-    wt, wm = B.pair_build(d, n, 1, L)
-    torch.cuda.synchronize()
-    del d
-    cap = orc.sel_capacity(n)
-    for kind, s in ((WT, wt), (WM, wm)):
-        assert s.status() == 0
-        bits, zeros, rd, s0, s1 = s.host_arrays()
-        ob, oz = orc.par_build(kind, T, L)
-        W = ob.shape[1]
-        assert np.array_equal(zeros, oz), f"kind {kind}: Z"
-        for l in range(L):
-            if not np.array_equal(bits[l], ob[l]):
-                bad = np.flatnonzero(bits[l] != ob[l])
-                raise AssertionError(f"kind {kind} level {l}: {bad.size} words differ, first {bad[0]}")
-            ord_, os0, os1 = orc.directory(ob[l], n)
-            assert np.array_equal(rd[l][: W // 8 + 1], ord_), f"kind {kind} rank_dir level {l}"
-            assert np.array_equal(s0[l][:cap], os0), f"kind {kind} sel0 level {l}"
-            assert np.array_equal(s1[l][:cap], os1), f"kind {kind} sel1 level {l}"
-        del bits, ob
-    del wt, wm
-    torch.cuda.empty_cache()
