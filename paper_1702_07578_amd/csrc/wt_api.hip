@@ -107,8 +107,7 @@ static int plan_text(uint64_t n, uint32_t b, uint32_t L, uint32_t kind, const wt
     const uint32_t target = (tune && tune->grid) ? tune->grid : kTargetRanges;
     d.R = (uint32_t)std::max<uint64_t>(1, cdiv64(d.ntiles, target));
     d.nranges = (uint32_t)cdiv64(d.ntiles, d.R);
-    d.CH = kBorderChunk;
-    d.nchunks = (uint32_t)cdiv64(d.nranges, d.CH);
+    d.nchunks = (uint32_t)cdiv64(d.nranges, kBorderChunk);
     d.W = words_per_level(n);
     d.nb = d.W / 8;
     d.rank_stride = rank_stride(n);

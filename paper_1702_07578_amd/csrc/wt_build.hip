@@ -206,14 +206,51 @@ __global__ __launch_bounds__(kTileThreads) void k_hist(const TextDesc *__restric
 }
 
 // ---------------------------------------------------------------------------
-// K1a: per chunk of kBorderChunk ranges, column sums of the range histograms
-// (several threads per key when the keys are fewer than the threads)
+// K1a: per chunk of kBorderChunk ranges, column sums of the range histograms.
+// The block's threads are P parts of each of the nk keys (thread p nk + k is
+// part p of key k, P nk = the block size); a part adds up to kPartRanges
+// ranges, with all of its loads issued before the first add.
 
-__global__ __launch_bounds__(256) void k_chunk_sum(const TextDesc *__restrict__ descs,
-                                                   const uint32_t *__restrict__ bases, uint32_t nd,
-                                                   uint32_t nitems, uint32_t g)
+constexpr uint32_t kSumThreads = 1024;
+constexpr uint32_t kPartRanges = 8;
+static_assert(kBorderChunk <= kPartRanges * (kSumThreads >> kMaxGroupBits),
+              "a part adds at most kPartRanges ranges of a chunk");
+
+// Sum of the P parts of every key, left in buf[k]; thread p nk + k brings
+// part p of key k (P a power of two, P nk = the block size).
+__device__ inline void parts_reduce(uint32_t s, uint32_t nk, uint32_t P, uint32_t *buf)
 {
-    __shared__ uint32_t part[256];
+    const uint32_t tid = threadIdx.x, p = tid / nk;
+    buf[tid] = s;
+    __syncthreads();
+    for (uint32_t half = P >> 1; half > 0; half >>= 1) {
+        if (p < half) buf[tid] += buf[tid + half * nk];
+        __syncthreads();
+    }
+}
+
+// Inclusive sum of parts 0..p of the thread's key (same layout), in
+// log2(P) steps.
+__device__ inline uint32_t parts_incl_scan(uint32_t s, uint32_t nk, uint32_t P, uint32_t *buf)
+{
+    const uint32_t tid = threadIdx.x, p = tid / nk;
+    buf[tid] = s;
+    __syncthreads();
+    for (uint32_t off = 1; off < P; off <<= 1) {
+        const uint32_t v = p >= off ? buf[tid - off * nk] : 0u;
+        __syncthreads();
+        s += v;
+        buf[tid] = s;
+        __syncthreads();
+    }
+    return s;
+}
+
+__global__ __launch_bounds__(kSumThreads) void k_chunk_sum(const TextDesc *__restrict__ descs,
+                                                           const uint32_t *__restrict__ bases, uint32_t nd,
+                                                           uint32_t nitems, uint32_t g)
+{
+    __shared__ uint32_t part[kSumThreads];
     for (uint32_t item = blockIdx.x; item < nitems; item += gridDim.x) {
         const uint32_t ti = find_text(bases, nd, item);
         const TextDesc &d = descs[ti];
@@ -221,18 +258,18 @@ __global__ __launch_bounds__(256) void k_chunk_sum(const TextDesc *__restrict__ 
         if (g >= d.G || c >= d.nchunks) continue;
         const uint32_t Kg = group_bits(d, g);
         if (Kg == 0) continue;
-        const uint32_t nk = 1u << Kg, P = blockDim.x / nk;  // parts per key (>= 1)
+        const uint32_t nk = 1u << Kg, P = kSumThreads / nk;
         const uint32_t k = threadIdx.x % nk, p = threadIdx.x / nk;
-        const uint32_t r0 = c * d.CH, r1 = min(d.nranges, r0 + d.CH);
+        const uint32_t r0 = c * kBorderChunk, r1 = min(d.nranges, r0 + kBorderChunk);  // r0 < r1
         uint32_t s = 0;
-        if (p < P)
-            for (uint32_t r = r0 + p; r < r1; r += P) s += gp(d.H)[(uint64_t)r * nk + k];
-        part[threadIdx.x] = s;
-        __syncthreads();
-        if (p == 0) {
-            for (uint32_t q = 1; q < P; q++) s += part[q * nk + k];
-            gp(d.CS)[(uint64_t)c * nk + k] = s;
+#pragma unroll
+        for (uint32_t i = 0; i < kPartRanges; i++) {
+            const uint32_t r = r0 + p + i * P;
+            const uint32_t x = gp(d.H)[(uint64_t)min(r, r1 - 1) * nk + k];
+            s += r < r1 ? x : 0u;
         }
+        parts_reduce(s, nk, P, part);
+        if (p == 0) gp(d.CS)[(uint64_t)c * nk + k] = part[k];
         __syncthreads();
     }
 }
@@ -255,6 +292,8 @@ __global__ __launch_bounds__(256) void k_chunk_sum(const TextDesc *__restrict__ 
 
 constexpr uint32_t kBorderThreads = 1024;
 constexpr uint32_t kBorderWaves = kBorderThreads / 64;
+static_assert(kBorderChunk <= kPartRanges * (kBorderThreads >> kMaxGroupBits),
+              "a part takes at most kPartRanges ranges of a chunk");
 
 __global__ __launch_bounds__(kBorderThreads) void k_borders(const TextDesc *__restrict__ descs,
                                                             const uint32_t *__restrict__ bases,
@@ -267,6 +306,7 @@ __global__ __launch_bounds__(kBorderThreads) void k_borders(const TextDesc *__re
     __shared__ uint32_t tot[2 * kK];
     __shared__ uint32_t kbid[2 * kK], kbpi[2 * kK];
     __shared__ uint32_t S[kBorderWaves][kK + 1];
+    __shared__ uint32_t tpl[kBorderChunk * kK];  // TP of the chunk's ranges
     const uint32_t tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     for (uint32_t item = blockIdx.x; item < nitems; item += gridDim.x) {
         const uint32_t ti = find_text(bases, nd, item);
@@ -280,26 +320,25 @@ __global__ __launch_bounds__(kBorderThreads) void k_borders(const TextDesc *__re
 
         // chunk prefix and totals of the finest keys
         uint32_t before = 0, all = 0;
-        // unrolled, so that several loads are in flight at once
-#pragma unroll 8
-        for (uint32_t c2 = p; c2 < d.nchunks; c2 += P) {
-            const uint32_t x = gp(d.CS)[(uint64_t)c2 * nk + k];
-            all += x;
-            if (c2 < c) before += x;
+        // a part's chunks c2 = p + i P, eight loads issued before their adds
+        for (uint32_t cb = p; cb < d.nchunks; cb += kPartRanges * P) {
+            uint32_t xs[kPartRanges];
+#pragma unroll
+            for (uint32_t i = 0; i < kPartRanges; i++)
+                xs[i] = gp(d.CS)[(uint64_t)min(cb + i * P, d.nchunks - 1) * nk + k];
+#pragma unroll
+            for (uint32_t i = 0; i < kPartRanges; i++) {
+                const uint32_t c2 = cb + i * P;
+                const uint32_t x = c2 < d.nchunks ? xs[i] : 0u;
+                all += x;
+                before += c2 < c ? x : 0u;
+            }
         }
-        part[tid] = before;
+        parts_reduce(before, nk, P, part);
+        if (p == 0) pre[k] = part[k];
         __syncthreads();
-        if (p == 0) {
-            for (uint32_t q = 1; q < P; q++) before += part[q * nk + k];
-            pre[k] = before;
-        }
-        __syncthreads();
-        part[tid] = all;
-        __syncthreads();
-        if (p == 0) {
-            for (uint32_t q = 1; q < P; q++) all += part[q * nk + k];
-            tot[lvl_off(Kg) + k] = all;
-        }
+        parts_reduce(all, nk, P, part);
+        if (p == 0) tot[lvl_off(Kg) + k] = part[k];
         __syncthreads();
         for (uint32_t a = Kg; a-- > 0;) {
             for (uint32_t kk = tid; kk < (1u << a); kk += kBorderThreads)
@@ -348,32 +387,41 @@ __global__ __launch_bounds__(kBorderThreads) void k_borders(const TextDesc *__re
                 }
             }
         }
-        // TP of the chunk's ranges: each part of a key takes consecutive ranges
-        const uint32_t r0 = c * d.CH, r1 = min(d.nranges, r0 + d.CH);
-        const uint32_t per = (d.CH + P - 1) / P;
+        // TP of the chunk's ranges: each part of a key takes up to kPartRanges
+        // consecutive ranges, loaded together; the chunk's TP is also kept in
+        // LDS for the shared words below
+        const uint32_t r0 = c * kBorderChunk, r1 = min(d.nranges, r0 + kBorderChunk);  // r0 < r1
+        const uint32_t per = (kBorderChunk + P - 1) / P;
         const uint32_t q0 = min(r1, r0 + p * per), q1 = min(r1, q0 + per);
-        uint32_t s = 0;
-        for (uint32_t r = q0; r < q1; r++) s += gp(d.H)[(uint64_t)r * nk + k];
-        part[tid] = s;
-        __syncthreads();
-        uint32_t run = pre[k];
-        for (uint32_t q = 0; q < p; q++) run += part[q * nk + k];
-        for (uint32_t r = q0; r < q1; r++) {
-            const uint32_t x = gp(d.H)[(uint64_t)r * nk + k];
-            gp(d.TP)[(uint64_t)r * nk + k] = run;
-            run += x;
+        uint32_t x[kPartRanges], s = 0;
+#pragma unroll
+        for (uint32_t i = 0; i < kPartRanges; i++) {
+            const uint32_t r = q0 + i;
+            x[i] = gp(d.H)[(uint64_t)min(r, r1 - 1) * nk + k];
+            x[i] = r < q1 ? x[i] : 0u;
+            s += x[i];
+        }
+        uint32_t run = pre[k] + parts_incl_scan(s, nk, P, part) - s;
+#pragma unroll
+        for (uint32_t i = 0; i < kPartRanges; i++) {
+            const uint32_t r = q0 + i;
+            if (r < q1) {
+                gp(d.TP)[(uint64_t)r * nk + k] = run;
+                tpl[(r - r0) * nk + k] = run;
+            }
+            run += x[i];
         }
         __syncthreads();
         // shared words of every range of the chunk (one wave per range)
         for (uint32_t r = r0 + w; r < r1; r += kBorderWaves) {
-            const uint32_t *tp = d.TP + (uint64_t)r * nk;
+            const uint32_t *tp = tpl + (r - r0) * nk;
             uint32_t *sw = S[w];
             uint32_t carry = 0;
             for (uint32_t base = 0; base < nk; base += 64) {
                 const uint32_t j = base + lane;
-                const uint32_t x = (j < nk) ? gp(tp)[j] : 0u;
-                const uint32_t incl = wave_incl_scan(x);
-                if (j < nk) sw[j] = carry + incl - x;
+                const uint32_t v = (j < nk) ? tp[j] : 0u;
+                const uint32_t incl = wave_incl_scan(v);
+                if (j < nk) sw[j] = carry + incl - v;
                 carry += last_lane(incl);
             }
             if (lane == 0) sw[nk] = carry;
@@ -607,7 +655,7 @@ hipError_t launch_group(const TextDesc *d_descs, const GroupLaunch &gl, const La
                        ctx.stream, d_descs, gl.range_bases, nd, gl.nranges, g);
     after(ctx, KID_HIST);
     if (!gl.any_levels) return hipGetLastError();
-    hipLaunchKernelGGL(k_chunk_sum, dim3(grid_for(gl.nchunks, gl.grid_cap)), dim3(256), 0,
+    hipLaunchKernelGGL(k_chunk_sum, dim3(grid_for(gl.nchunks, gl.grid_cap)), dim3(kSumThreads), 0,
                        ctx.stream, d_descs, gl.chunk_bases, nd, gl.nchunks, g);
     after(ctx, KID_CHUNK_SUM);
     hipLaunchKernelGGL(k_borders, dim3(grid_for(gl.nchunks, gl.grid_cap)), dim3(kBorderThreads), 0,

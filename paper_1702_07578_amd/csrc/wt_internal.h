@@ -44,8 +44,7 @@ struct TextDesc {
     uint32_t log2S; // log2 symbols per tile
     uint32_t ntiles;
     uint32_t R;          // tiles per range; one scatter wave walks a range in order
-    uint32_t CH;         // ranges per chunk (column scan)
-    uint32_t nchunks;
+    uint32_t nchunks;    // chunks of kBorderChunk ranges (column scan)
     uint32_t dir_chunks; // directory chunks per level
     uint32_t nranges;
     uint64_t W;  // words per level
@@ -60,7 +59,7 @@ struct TextDesc {
     // workspace
     uint32_t *H;   // [nranges][2^K] per-range histogram of the group key
     uint32_t *TP;  // [nranges][2^K] range-exclusive prefix of H per key
-    uint32_t *CS;  // [nchunks][2^K] chunk sums -> chunk-exclusive prefixes
+    uint32_t *CS;  // [nchunks][2^K] chunk sums
     uint32_t *KBid, *KBpi; // [2^(K+1)] key bases per group level, prefix / reversed order
     uint32_t *HT;  // [2^(K+1)] per group level key totals
     void *seqA, *seqB;     // reordered text between groups (n symbols each)

@@ -9,6 +9,9 @@ oracle's per-position definition, access at sampled positions, and rank and
 select against counts and each other.  The pair build (both structures of
 the text, the benchmark's step) must write exactly the same outputs as the
 checked separate builds."""
+import os
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 import pytest
 
@@ -44,27 +47,32 @@ def _check_structure(orc, T, L, kind, s, rng):
     del ob
     assert np.array_equal(zeros, _zero_counts(T, L)), "zero counts"
     pos = np.sort(rng.integers(0, n, size=SAMPLES, dtype=np.uint64))
-    for l in range(L):
-        lv = bits[l]
-        # popcount of the level = symbols whose bit l is 1
-        assert int(np.bitwise_count(lv).sum()) == n - int(zeros[l]), f"level {l} popcount"
-        # bits past n are zero
-        if n % 64:
-            assert int(lv[n // 64]) >> (n % 64) == 0, f"level {l} tail bits"
-        assert not lv[(n + 63) // 64:].any(), f"level {l} padding words"
-        # directories: the oracle's, of this level's words (equal to the
-        # oracle's own levels, checked above)
-        ord_, os0, os1 = orc.directory(lv, n)
+    # the oracle's per-level routines release the interpreter lock, so the
+    # levels are checked on several host threads at once
+    workers = max(1, min(L, os.cpu_count() or 1, 16))
+    with ThreadPoolExecutor(workers) as ex:
+        dirs = ex.map(lambda l: orc.directory(bits[l], n), range(L))
+        lv_sample = sorted({0, L // 2, L - 1})
+        samples = ex.map(lambda l: orc.sample_level(kind, T, L, l, pos), lv_sample)
         cap = orc.sel_capacity(n)
-        assert np.array_equal(rd[l][: W // 8 + 1], ord_), f"rank_dir level {l}"
-        assert np.array_equal(s0[l][:cap], os0), f"sel0 level {l}"
-        assert np.array_equal(s1[l][:cap], os1), f"sel1 level {l}"
-    # level bits at sampled positions: the oracle's per-position definition
-    for l in sorted({0, L // 2, L - 1}):
-        want = orc.sample_level(kind, T, L, l, pos)
-        got = ((bits[l][(pos >> 6).astype(np.int64)] >> (pos & 63)) & 1).astype(np.uint8)
-        bad = np.flatnonzero(got != want)
-        assert bad.size == 0, f"kind {kind} level {l}: {bad.size} of {SAMPLES} sampled bits differ"
+        for l, (ord_, os0, os1) in zip(range(L), dirs):
+            lv = bits[l]
+            # popcount of the level = symbols whose bit l is 1
+            assert int(np.bitwise_count(lv).sum()) == n - int(zeros[l]), f"level {l} popcount"
+            # bits past n are zero
+            if n % 64:
+                assert int(lv[n // 64]) >> (n % 64) == 0, f"level {l} tail bits"
+            assert not lv[(n + 63) // 64:].any(), f"level {l} padding words"
+            # directories: the oracle's, of this level's words (equal to the
+            # oracle's own levels, checked above)
+            assert np.array_equal(rd[l][: W // 8 + 1], ord_), f"rank_dir level {l}"
+            assert np.array_equal(s0[l][:cap], os0), f"sel0 level {l}"
+            assert np.array_equal(s1[l][:cap], os1), f"sel1 level {l}"
+        # level bits at sampled positions: the oracle's per-position definition
+        for l, want in zip(lv_sample, samples):
+            got = ((bits[l][(pos >> 6).astype(np.int64)] >> (pos & 63)) & 1).astype(np.uint8)
+            bad = np.flatnonzero(got != want)
+            assert bad.size == 0, f"kind {kind} level {l}: {bad.size} of {SAMPLES} sampled bits differ"
 
 
 def _check_access(T, s, rng):
