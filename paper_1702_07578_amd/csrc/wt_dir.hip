@@ -52,15 +52,19 @@ __global__ __launch_bounds__(256) void k_dir_count(const TextDesc *__restrict__ 
         const gmem<ulonglong2> *p = gp((const ulonglong2 *)bits) + (uint64_t)c * kUnits;
         const uint64_t nblk = min((uint64_t)kDirChunk, d.nb - (uint64_t)c * kDirChunk);
         const uint32_t units = (uint32_t)nblk * 4;
+        // every load of the thread is issued before the first count: units
+        // past the chunk's end re-read its last unit (no branch per load)
         uint32_t x[kIters];
+        if (units != 0) {
 #pragma unroll
-        for (uint32_t r = 0; r < kIters; r++) {
-            const uint32_t u = r * 256 + threadIdx.x;
-            x[r] = 0;
-            if (u < units) {
-                const ulonglong2 v = load_nt(p + u);  // each level word is read once here
-                x[r] = __popcll(v.x) + __popcll(v.y);
+            for (uint32_t r = 0; r < kIters; r++) {
+                const uint32_t u = r * 256 + threadIdx.x;
+                const ulonglong2 v = load_nt(p + min(u, units - 1));  // each level word is read once here
+                x[r] = u < units ? __popcll(v.x) + __popcll(v.y) : 0u;
             }
+        } else {
+#pragma unroll
+            for (uint32_t r = 0; r < kIters; r++) x[r] = 0;
         }
         uint32_t sum = 0;
 #pragma unroll
