@@ -128,9 +128,22 @@ __device__ void hist_range(const TextDesc &d, uint32_t g, uint32_t Kg, uint32_t 
         const gmem<uint4> *u = gp((const uint4 *)src);
         const uint64_t nu = len / per_unit;
         uint64_t i = tid;
-        for (; i + 3 * kTileThreads < nu; i += 4 * kTileThreads) {
-            const uint4 a0 = u[i], a1 = u[i + kTileThreads], a2 = u[i + 2 * kTileThreads],
-                        a3 = u[i + 3 * kTileThreads];
+        // four units per step, the next four loaded before the current ones
+        // are counted
+        if (i + 3 * kTileThreads < nu) {
+            uint4 a0 = u[i], a1 = u[i + kTileThreads], a2 = u[i + 2 * kTileThreads], a3 = u[i + 3 * kTileThreads];
+            for (i += 4 * kTileThreads; i + 3 * kTileThreads < nu; i += 4 * kTileThreads) {
+                const uint4 b0 = u[i], b1 = u[i + kTileThreads], b2 = u[i + 2 * kTileThreads],
+                            b3 = u[i + 3 * kTileThreads];
+                count_unit<E, lc>(a0, kshift, kw, himask, bad, hist);
+                count_unit<E, lc>(a1, kshift, kw, himask, bad, hist);
+                count_unit<E, lc>(a2, kshift, kw, himask, bad, hist);
+                count_unit<E, lc>(a3, kshift, kw, himask, bad, hist);
+                a0 = b0;
+                a1 = b1;
+                a2 = b2;
+                a3 = b3;
+            }
             count_unit<E, lc>(a0, kshift, kw, himask, bad, hist);
             count_unit<E, lc>(a1, kshift, kw, himask, bad, hist);
             count_unit<E, lc>(a2, kshift, kw, himask, bad, hist);
@@ -180,7 +193,7 @@ __device__ void hist_range(const TextDesc &d, uint32_t g, uint32_t Kg, uint32_t 
     if (tid < nk) gp(H)[tid] = sh[tid];
 }
 
-__global__ __launch_bounds__(kTileThreads) void k_hist(const TextDesc *__restrict__ descs,
+__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(5))) void k_hist(const TextDesc *__restrict__ descs,
                                                        const uint32_t *__restrict__ bases,
                                                        uint32_t nd, uint32_t nitems, uint32_t g)
 {
