@@ -206,13 +206,26 @@ __device__ inline uint32_t last_lane(uint32_t x) { return __builtin_amdgcn_readl
 __device__ inline uint64_t rank1_dir(const uint64_t *__restrict__ bits, const uint32_t *__restrict__ rd,
                                      uint64_t i)
 {
-    uint64_t blk = i >> 9;
-    uint64_t r = rd[blk];
-    uint64_t wi = i >> 6;
-    for (uint64_t w = blk * 8; w < wi; w++) r += __popcll(bits[w]);
-    uint32_t rem = (uint32_t)(i & 63);
-    if (rem) r += __popcll(bits[wi] & ((1ull << rem) - 1));
-    return r;
+    const uint64_t blk = i >> 9;
+    const uint32_t before = rd[blk];
+    // words of the block before position i (the last one partly)
+    const uint32_t wi = (uint32_t)(i >> 6) & 7u, rem = (uint32_t)(i & 63);
+    const uint32_t need = wi + (rem != 0);
+    uint32_t part = 0;
+    if (need != 0) {
+        // all loads issued before the first count; word k >= need re-reads
+        // word need - 1 (no word past those the count reads) and is masked out
+        const uint64_t *b = bits + blk * 8;
+        uint64_t w[8];
+#pragma unroll
+        for (uint32_t k = 0; k < 8; k++) w[k] = b[min(k, need - 1)];
+#pragma unroll
+        for (uint32_t k = 0; k < 8; k++) {
+            const uint64_t m = k < wi ? ~0ull : (k == wi ? (1ull << rem) - 1 : 0ull);
+            part += __popcll(w[k] & m);
+        }
+    }
+    return (uint64_t)before + part;
 }
 
 }  // namespace wtg

@@ -131,7 +131,14 @@ __global__ __launch_bounds__(256) void k_dir_write(const TextDesc *__restrict__ 
         // counts, added up by the whole block
         const gmem<uint32_t> *cs = gp(d.dir_cs + (uint64_t)l * d.dir_chunks);
         uint32_t before = 0;
-        for (uint32_t i = tid; i < c; i += 256) before += cs[i];
+        // eight loads issued before their adds (indices past c - 1 re-read it)
+        for (uint32_t i0 = tid; i0 < c; i0 += 8 * 256) {
+            uint32_t xs[8];
+#pragma unroll
+            for (uint32_t k = 0; k < 8; k++) xs[k] = cs[min(i0 + k * 256, c - 1)];
+#pragma unroll
+            for (uint32_t k = 0; k < 8; k++) before += i0 + k * 256 < c ? xs[k] : 0u;
+        }
         before = wave_incl_scan(before);
         const uint32_t incl = wave_incl_scan(s);
         if (lane == 63) {

@@ -82,7 +82,13 @@ __device__ uint64_t select_b(const QLevel &q, uint64_t n, uint64_t nb, uint64_t 
         else hi = mid - 1;
     }
     uint64_t r = k - before(lo);
-    const uint64_t *w = q.bits + lo * 8;
+    // the block's 8 words (lo < nb: the block lies inside the level), all
+    // loaded before the scan
+    const uint64_t *wp = q.bits + lo * 8;
+    uint64_t w[8];
+#pragma unroll
+    for (uint32_t i = 0; i < 8; i++) w[i] = wp[i];
+#pragma unroll
     for (uint32_t i = 0; i < 8; i++) {
         const uint64_t x = b ? w[i] : ~w[i];
         const uint32_t c = __popcll(x);
