@@ -484,9 +484,10 @@ __global__ __launch_bounds__(256) void k_walk(const TextDesc *__restrict__ descs
     if (item >= nitems) return;
     const TextDesc &d = descs[ti];
     const uint32_t p = item - item_base(bases, nd, ti);
-    // the fields the test needs, loaded together (no branch between loads)
+    // the fields the test needs, loaded together (no branch between loads);
+    // l + 1 < L <= 32 before the shift
     const uint32_t kind = d.kind, G = d.G, L = d.L, l = d.K + step;
-    if ((kind != WT_TREE) | (G <= 1) | (l + 1 >= L) | (p >= (1u << l))) return;
+    if (((kind != WT_TREE) | (G <= 1) | (l + 1 >= L)) || p >= (1u << l)) return;
     const uint32_t np = 1u << l;
     const uint32_t *cur = d.walk + walk_off(d.K, l);
     uint32_t *nxt = d.walk + walk_off(d.K, l + 1);
