@@ -57,3 +57,26 @@ def test_access_reconstructs_text():
         pos = torch.arange(T.size, dtype=torch.int64, device="cuda")
         acc = s.access(pos).cpu().numpy().view(np.uint32)
         assert np.array_equal(acc, T.astype(np.uint32))
+
+
+@pytest.mark.parametrize("n", [4096, 4097, 4159, 5119])
+@pytest.mark.parametrize("kind", [0, 1])
+def test_every_position_and_every_k(orc, n, kind):
+    """rank of every symbol at every position 0..n (block starts, word starts,
+    the ends of whole and ragged texts) and select of every symbol for every k
+    from 1 to one past its count, against the oracle's definitions."""
+    import torch
+    L = 3
+    rng = np.random.default_rng(n + kind)
+    T = rng.integers(0, 1 << L, size=n, dtype=np.uint64).astype(np.uint8)
+    s = gpu_build(T, L, kind)
+    syms = np.repeat(np.arange(1 << L, dtype=np.uint32), n + 1)
+    pos = np.tile(np.arange(n + 1, dtype=np.uint64), 1 << L)
+    dev = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a).view(dt)).cuda()
+    rk = s.rank(dev(syms, np.int32), dev(pos, np.int64)).cpu().numpy().view(np.uint64)
+    assert np.array_equal(rk, orc.queries_def(T, L, 1, syms, pos))
+    counts = np.bincount(T, minlength=1 << L)
+    ssym = np.concatenate([np.full(int(c) + 1, a, dtype=np.uint32) for a, c in enumerate(counts)])
+    kk = np.concatenate([np.arange(1, int(c) + 2, dtype=np.uint64) for c in counts])
+    sl = s.select(dev(ssym, np.int32), dev(kk, np.int64)).cpu().numpy().view(np.uint64)
+    assert np.array_equal(sl, orc.queries_def(T, L, 2, ssym, kk))
